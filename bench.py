@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Throughput of Bahmani (2+2eps) peeling on one MI355X.
+
+One step = one complete peel of the workload graph (init, every pass's mark
+and neighbour walk, extraction of S~), with the CSR already resident in HBM.
+The metric is peeled edges per second, GTEPS = m / t_step, next to the
+fraction of the HBM roofline that the dominant kernel (the neighbour walk)
+reaches, and the CPU oracle timed on the host's cores.
+
+Default workload: R-MAT scale 24 (n = 16,777,216), edge factor 16,
+(a,b,c,d) = (.57,.19,.19,.05), seed 0, plus a planted G(2000, 1/2) block on
+random ids (seed 1), eps = 1/10 - the largest single-graph configuration.
+
+Prints exactly one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parent
+if str(ROOT) not in sys.path:
+    sys.path.insert(0, str(ROOT))
+
+METRIC = "peeled edges/sec (GTEPS) + % HBM roofline; batched graphs/sec vs 1-graph/launch"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = ROOT / "profiles" / "walk_traffic_rmat24.json"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name: str):
+    from paper_2103_00154_amd import inputs
+    if name == "rmat24":
+        g = inputs.rmat(24, 16, seed=0, planted=(2000, 0.5, 1))
+        desc = ("R-MAT scale 24, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 0, "
+                "planted G(2000,1/2) on random ids (seed 1)")
+    elif name == "rmat20":
+        g = inputs.rmat(20, 16, seed=0)
+        desc = "R-MAT scale 20, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 0"
+    elif name == "er10k":
+        g = inputs.erdos_renyi(10_000, 50_000, 0)
+        desc = "Erdos-Renyi n=10000 m=50000, seed 0"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return g, desc
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for p in sorted((ROOT / "paper_2103_00154_amd" / "csrc").glob("*")):
+        h.update(p.read_bytes())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload: str, launches: int):
+    """HBM bytes per walk launch measured with rocprofv3 counters, if they
+    were taken on the current kernel source."""
+    if not TRAFFIC_FILE.exists():
+        return None
+    try:
+        rec = json.loads(TRAFFIC_FILE.read_text())
+    except ValueError:
+        return None
+    if rec.get("kernel_digest") != kernel_source_digest() or rec.get("workload") != workload:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat24", choices=["rmat24", "rmat20", "er10k"])
+    ap.add_argument("--eps", default="1/10")
+    ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} (WORLD_SIZE {world}) is not "
+              "supported by this build: the peel of one graph runs on a single MI355X.",
+              file=sys.stderr)
+        return 2
+
+    num, den = (int(x) for x in args.eps.split("/"))
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        return 1
+    from paper_2103_00154_amd import dsg
+
+    t0 = time.time()
+    g, desc = make_workload(args.workload)
+    log(f"workload {args.workload}: n={g.n} m={g.m} generated in {time.time() - t0:.1f}s")
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    ci = torch.from_numpy(g.col_idx).to(dev)
+    ws = dsg.alloc_workspace(g.n, g.m, dev)
+    best = torch.empty(g.n, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        r = dsg.peel(rp, ci, (num, den), best_ids=best, workspace=ws)
+    torch.cuda.synchronize()
+
+    walk_ms = 0.0
+    walk_launches = 0
+    walked = cross = walk_list = live = 0
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        r = dsg.peel(rp, ci, (num, den), best_ids=best, workspace=ws, profile=True)
+        p = r.profile
+        walk_ms += p["ms_walk"]
+        walk_launches += p["launches_walk"]
+        walked += p["walked"]
+        cross += p["cross"]
+        walk_list += p["walk_list"]
+        live += p["live_scanned"]
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    ms_per_step = (t_end - t_start) * 1e3 / args.steps
+    gteps = g.m / (ms_per_step * 1e-3) / 1e9
+    log(f"GPU: {ms_per_step:.3f} ms/step, {gteps:.1f} GTEPS, passes={r.passes} "
+        f"best={r.num}/{r.den} (pass {r.best_pass})")
+
+    # walk kernel: algorithmic bytes = 4 B column id + 4 B neighbour state per
+    # walked entry, 8 B read-modify-write per degree decrement, and 12 B per
+    # walk-list row (id, prefix offset, row start)
+    walk_bytes = 8 * walked + 8 * cross + 12 * walk_list
+    per_launch_bytes = walk_bytes / walk_launches
+    per_launch_ms = walk_ms / walk_launches
+    achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+    traffic = stored_traffic(args.workload, walk_launches // args.steps)
+    # whole path: walk bytes plus 12 B per live-list test (id, degree,
+    # re-write) and 24 B per vertex (row_ptr pair, init writes, removal pass,
+    # extraction read)
+    path_bytes = (walk_bytes + 12 * live) / args.steps + 24 * g.n
+    path_gbs = path_bytes / (ms_per_step * 1e-3) / 1e9
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        times = []
+        o = None
+        for _ in range(args.cpu_reps):
+            c0 = time.perf_counter()
+            o = oracle.peel_graph(g, num, den, trace=False)
+            times.append(time.perf_counter() - c0)
+        t_cpu = statistics.median(times)
+        cpu = {"value": round(g.m / t_cpu / 1e9, 4), "unit": "GTEPS", "cores": 1,
+               "kind": "oracle",
+               "sample": f"whole workload (n={g.n}, m={g.m}), single-threaded C oracle, "
+                         f"median of {args.cpu_reps} runs, {t_cpu:.2f} s each"}
+        same = ((r.passes, r.best_pass, r.num, r.den) == (o.passes, o.best_pass, o.num, o.den)
+                and bool((best[:r.den].cpu().numpy() == o.best).all()))
+        parity = "exact" if same else "MISMATCH"
+        log(f"oracle: {t_cpu:.2f} s ({g.m / t_cpu / 1e9:.3f} GTEPS), parity {parity}")
+
+    line = {
+        "metric": METRIC,
+        "value": round(gteps, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}, eps={num}/{den}", "n": g.n,
+                   "m": g.m, "eps": f"{num}/{den}", "passes": r.passes,
+                   "launch": "library default", "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_walk",
+                     "launches_per_step": walk_launches // args.steps,
+                     "ms_per_launch": round(per_launch_ms, 4),
+                     "alg_bytes_per_launch": int(per_launch_bytes)},
+        "path_roofline": {"achieved": round(path_gbs, 1), "unit": "GB/s",
+                          "frac": round(path_gbs / HBM_PEAK_GBS, 4),
+                          "alg_bytes_per_step": int(path_bytes)},
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(line), flush=True)
+    return 0 if parity in (None, "exact") else 3
+
+
+if __name__ == "__main__":
+    sys.exit(main())

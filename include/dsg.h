@@ -1,0 +1,178 @@
+/*
+ * dsg.h - C ABI of libdsg.so: Bahmani's (2+2eps)-approximate densest
+ * subgraph peeling on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (Section 3.1 of De Zoysa et al., "Parallel Algorithms for Densest
+ * Subgraph Discovery Using Shared Memory Model", Algorithm 1 "P-Bahmani";
+ * the approximation algorithm of Bahmani, Kumar and Vassilvitskii it
+ * parallelises): the current graph starts as G.  Each pass removes, all at
+ * once, every vertex whose degree inside the current graph is at most
+ * 2(1+eps) times the current edge density rho = |E| / |V| (Definition 1),
+ * decrements the degrees of their surviving neighbours, and keeps the
+ * densest intermediate graph seen so far.  Passes repeat until no vertex is
+ * left.  The kept graph S~ satisfies rho(S~) >= rho*(G) / (2 + 2 eps)
+ * (Definition 3) and O(log_{1+eps} n) passes suffice.
+ *
+ * Exactness: eps = eps_num / eps_den is a rational and every test is done in
+ * integers.  A vertex of degree d fails a pass that starts with |V| vertices
+ * and |E| edges when d * |V| * eps_den <= 2 (eps_num + eps_den) |E|.  An edge
+ * whose two ends fail in the same pass is removed once.  The whole graph is
+ * the pass-0 candidate; a later graph replaces the best only when its density
+ * is strictly larger.  "passes" counts every pass, including the one that
+ * empties the graph.  Results are fully deterministic (no floating point, no
+ * order dependence).
+ *
+ * Input graph: vertices 0..n-1, undirected, simple, stored as a symmetric
+ * int32 CSR (both directions of every edge) with ascending neighbours in
+ * every row and no self loops.  row_ptr has n+1 entries with row_ptr[0] = 0
+ * and row_ptr[n] = 2m.  Isolated vertices count in n.
+ *
+ * Memory: pointers documented as "device" must point to device memory of the
+ * current HIP device; "host" pointers to host memory.  The library never
+ * frees or keeps caller memory.  Calls with distinct workspaces may run
+ * concurrently on different streams.
+ *
+ * Errors: every entry point returns DSG_OK (0) or a negative dsg_status.
+ * Argument checks run before any HIP call.  No C++ exception crosses this
+ * boundary.
+ */
+#ifndef DSG_H
+#define DSG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DSG_OK = 0,
+    DSG_EINVAL = -1,      /* bad argument, too small workspace, or an input
+                             that violates the CSR contract when detected */
+    DSG_EOVERFLOW = -2,   /* sizes or eps outside the exact int64 range */
+    DSG_ENOMEM = -3,      /* device allocation failed */
+    DSG_EDEVICE = -4,     /* a HIP runtime call failed */
+    DSG_EINTERNAL = -5    /* pass watchdog or invariant check tripped */
+} dsg_status;
+
+/* Graph in device memory, borrowed read-only for the duration of a call. */
+typedef struct {
+    const int32_t* row_ptr; /* device, n+1 entries */
+    const int32_t* col_idx; /* device, 2m entries */
+} dsg_csr;
+
+/* Result of one peel (host struct). */
+typedef struct {
+    int64_t dens_num;  /* |E(S~)|, unreduced numerator of rho(S~)        */
+    int64_t dens_den;  /* |S~|, unreduced denominator (0 only when n = 0) */
+    int32_t passes;    /* passes until the graph was empty (0 when n = 0) */
+    int32_t best_pass; /* S~ is the graph left after this pass (0 = G)    */
+    int64_t best_size; /* |S~| = number of ids written to best_ids         */
+} dsg_result;
+
+/* One pass, as recorded when a trace is requested (host struct). */
+typedef struct {
+    int64_t s_in;    /* |V| at the start of the pass */
+    int64_t e_in;    /* |E| at the start of the pass */
+    int64_t thresh;  /* floor(2(num+den)|E| / (|V| den)), capped at INT32_MAX */
+    int64_t removed; /* vertices that failed */
+    int64_t cross;   /* adjacency entries from failed vertices to survivors */
+    int64_t intra;   /* adjacency entries between failed vertices (even)   */
+    int64_t walked;  /* adjacency entries the GPU walked in this pass      */
+    int64_t s_out;   /* |V| after the pass */
+    int64_t e_out;   /* |E| after the pass */
+} dsg_pass_trace;
+
+/* Launch shape overrides; 0 selects the library default.  Results never
+ * depend on these. */
+typedef struct {
+    int32_t mark_grid;  /* workgroups of the mark / extract kernels */
+    int32_t walk_grid;  /* workgroups of the neighbour-walk kernel  */
+    int32_t pass_batch; /* passes enqueued before the host checks for completion */
+    int32_t reserved;
+} dsg_launch;
+
+/* Optional per-kernel timing, measured with HIP events on the call's stream
+ * around every launch of the call (host struct, filled on return). */
+typedef struct {
+    double ms_init;     /* init kernel */
+    double ms_mark;     /* mark-count + tile-scan + mark-scatter kernels */
+    double ms_walk;     /* neighbour-walk kernels (the dominant kernel) */
+    double ms_extract;  /* extract kernels */
+    double ms_total;    /* first launch to last kernel end */
+    int32_t launches_walk;  /* walk launches timed (includes no-op launches
+                               enqueued after the last pass) */
+    int32_t launches_mark;
+    int64_t walked;     /* adjacency entries walked over all passes */
+    int64_t cross;      /* degree decrements over all passes */
+    int64_t live_scanned; /* live-list entries tested over all passes */
+    int64_t walk_list;  /* failed vertices whose rows were walked, all passes */
+} dsg_profile;
+
+/* Library ABI version (increments on any incompatible change). */
+int32_t dsg_version(void);
+
+/* Human-readable text of a dsg_status; never NULL. */
+const char* dsg_strerror(int32_t status);
+
+/* Bytes of device workspace dsg_peel needs for a graph with n vertices and
+ * m undirected edges; 0 for invalid sizes.  About 24 n bytes. */
+size_t dsg_workspace_bytes(int64_t n, int64_t m);
+
+/*
+ * Peel g with eps = eps_num / eps_den (eps_num >= 0, eps_den >= 1) and
+ * return S~ and its density.
+ *
+ *   g           CSR as above (device pointers).
+ *   n, m        vertices and undirected edges; the kernels check
+ *               row_ptr[0] = 0 and row_ptr[n] = 2m (DSG_EINVAL otherwise).
+ *   best_ids    device, room for n int32; receives S~ in ascending order
+ *               (out->best_size entries).  May be NULL to skip extraction.
+ *   out         host; filled on DSG_OK.
+ *   workspace   device, at least dsg_workspace_bytes(n, m) bytes, 256-byte
+ *               aligned; NULL makes the library allocate and free it.
+ *   stream      a hipStream_t (NULL = the null stream).  All device work is
+ *               ordered on it; the call returns after *out is valid.
+ *
+ * Errors: DSG_EINVAL for NULL pointers where data is needed, n < 0, m < 0,
+ * eps_den < 1, eps_num < 0 or a short workspace; DSG_EOVERFLOW when
+ * n > INT32_MAX - 1, 2m > INT32_MAX, 2(eps_num + eps_den) m >= 2^63 or
+ * n eps_den >= 2^63; DSG_EDEVICE / DSG_ENOMEM for HIP failures;
+ * DSG_EINTERNAL when the pass watchdog (more passes than the
+ * O(log_{1+eps} n) bound of Section 3.1 allows) or an edge-count invariant
+ * trips, which only an input violating the CSR contract can cause.
+ */
+int32_t dsg_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_t eps_den,
+                 int32_t* best_ids, dsg_result* out, void* workspace, size_t ws_bytes,
+                 void* stream);
+
+/*
+ * dsg_peel with optional extras (each may be NULL / 0):
+ *   removed_at  device, n int32: the pass in which each vertex failed
+ *               (S~ = { v : removed_at[v] > best_pass }).
+ *   trace       host, trace_cap records: one dsg_pass_trace per pass, for
+ *               the first min(passes, trace_cap, 4096) passes.
+ *   launch      host: launch shape overrides.
+ *   prof        host: per-kernel timing (adds HIP events between launches).
+ */
+int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_t eps_den,
+                    int32_t* best_ids, int32_t* removed_at, dsg_result* out,
+                    dsg_pass_trace* trace, int32_t trace_cap, const dsg_launch* launch,
+                    dsg_profile* prof, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Check on the device that g satisfies the input contract above (O(m log d)
+ * work; for debugging and loaders).  Returns DSG_OK, DSG_EINVAL with
+ * *detail set to the first violated rule (1 row_ptr[0] != 0, 2 row_ptr not
+ * monotone, 3 row_ptr[n] != 2m, 4 neighbour id out of range, 5 self loop,
+ * 6 row not strictly ascending, 7 missing reverse edge), or a HIP error.
+ * `detail` (host) may be NULL.  Allocates a few bytes of device memory.
+ */
+int32_t dsg_validate_csr(const dsg_csr* g, int64_t n, int64_t m, int32_t* detail, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSG_H */

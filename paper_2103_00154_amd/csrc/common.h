@@ -1,0 +1,158 @@
+// common.h - device-side state, workspace layout and wave64 helpers shared by
+// the HIP translation units of libdsg.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dsg {
+
+constexpr int kBlock = 256;                      // threads per workgroup (4 wave64)
+constexpr int kWaves = kBlock / 64;
+constexpr int kMarkItems = 8;                    // live-list entries per thread
+constexpr int kMarkTile = kBlock * kMarkItems;   // live-list entries per tile
+constexpr int kWalkItems = 8;                    // adjacency entries per thread
+constexpr int kWalkTile = kBlock * kWalkItems;   // adjacency entries per tile
+constexpr int kTraceCap = 4096;                  // device trace records
+constexpr int32_t kNever = INT32_MAX;            // removed_at of a vertex still present
+
+// Device status codes (kept in DevState::status; mapped to dsg_status).
+enum : int32_t {
+    kStOk = 0,
+    kStBadRowPtr = 1,    // row_ptr[0] != 0 or row_ptr[n] != 2m
+    kStWatchdog = 2,     // more passes than the bound allows
+    kStInvariant = 3,    // intra-pass edge count odd or negative, or E < 0
+    kStExtract = 4,      // extracted set size differs from the best size
+};
+
+// Peeling state of one call, resident in the workspace.  Written by the
+// init kernel and by the single thread that finishes each pass; read by
+// every kernel at its start (kernel boundaries order these accesses).
+struct alignas(256) DevState {
+    int64_t S;          // |V| at the start of the current pass
+    int64_t E;          // |E| at the start of the current pass
+    int64_t best_E;     // |E(S~)| so far
+    int64_t best_S;     // |S~| so far
+    int64_t eps_num;
+    int64_t eps_den;
+    int64_t nA;         // failed vertices with degree > 0 in this pass (walk list)
+    int64_t nL;         // survivors of this pass
+    int64_t edges;      // adjacency entries of the walk list
+    int64_t sumdeg;     // sum of the current degrees of all failed vertices
+    unsigned long long cross;  // survivors' degree decrements, summed by walk blocks
+    int64_t best_count; // ids written by the extract kernels
+    int64_t tot_walked; // statistics over all passes
+    int64_t tot_cross;
+    int64_t tot_live;
+    int64_t tot_alist;
+    int32_t pass;       // number of the pass being run (1-based)
+    int32_t T;          // threshold of the current pass
+    int32_t best_pass;
+    int32_t done;       // 1 once the graph is empty or an error is recorded
+    int32_t status;
+    uint32_t ticket;    // last-block-done counter of the walk kernel
+    int32_t max_pass;   // watchdog bound
+    int32_t trace_cap;  // records the device trace may hold
+    int32_t n_tiles_walk;  // walk tiles of the current pass
+    int32_t pad[1];
+};
+
+struct PassRecord {
+    int64_t s_in, e_in, thresh, removed, cross, intra, walked, s_out, e_out;
+};
+
+// floor(2 (num + den) E / (S den)) capped at INT32_MAX.  The host checks
+// 2(num+den)m < 2^63 and n den < 2^63, so no product overflows.
+__device__ __host__ inline int32_t pass_threshold(int64_t E, int64_t S, int64_t num,
+                                                  int64_t den) {
+    const int64_t a = 2 * (num + den) * E;
+    const int64_t b = S * den;
+    const int64_t q = a / b;
+    return q > (int64_t)INT32_MAX ? INT32_MAX : (int32_t)q;
+}
+
+// ---------------------------------------------------------------- wave64
+
+__device__ inline int lane_id() { return threadIdx.x & 63; }
+__device__ inline int wave_id() { return threadIdx.x >> 6; }
+
+template <typename T>
+__device__ inline T wave_sum(T x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+template <typename T>
+__device__ inline T wave_incl_sum(T x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+__device__ inline int32_t wave_incl_max(int32_t x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x = max(x, y);
+    }
+    return x;
+}
+
+// Block-wide exclusive sum; *total receives the block sum.  `red` holds
+// kWaves elements of LDS.  Contains two barriers.
+template <typename T>
+__device__ inline T block_excl_sum(T x, T* red, T* total) {
+    const T incl = wave_incl_sum(x);
+    if (lane_id() == 63) red[wave_id()] = incl;
+    __syncthreads();
+    T before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const T v = red[w];
+        before += (w < wave_id()) ? v : T(0);
+        all += v;
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - x;
+}
+
+// Block-wide sum returned to every thread.  Two barriers.
+template <typename T>
+__device__ inline T block_sum(T x, T* red) {
+    x = wave_sum(x);
+    if (lane_id() == 0) red[wave_id()] = x;
+    __syncthreads();
+    T all = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) all += red[w];
+    __syncthreads();
+    return all;
+}
+
+// Block-wide exclusive max (identity `lo`).  Two barriers.
+__device__ inline int32_t block_excl_max(int32_t x, int32_t* red, int32_t lo) {
+    const int32_t incl = wave_incl_max(x);
+    int32_t excl_in_wave = __shfl_up(incl, 1, 64);
+    if (lane_id() == 0) excl_in_wave = lo;
+    if (lane_id() == 63) red[wave_id()] = incl;
+    __syncthreads();
+    int32_t before = lo;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w)
+        if (w < wave_id()) before = max(before, red[w]);
+    __syncthreads();
+    return max(before, excl_in_wave);
+}
+
+__device__ inline unsigned long long atomic_load_u64(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace dsg

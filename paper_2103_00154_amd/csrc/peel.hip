@@ -1,0 +1,835 @@
+// peel.hip - Bahmani's (2+2eps) peeling passes on gfx950 and the C ABI of
+// libdsg.so (include/dsg.h).
+//
+// One pass of Algorithm 1 (P-Bahmani, Section 3.1) maps onto four kernels
+// that run back to back on the caller's stream:
+//
+//   k_mark_count    part 1, the failure test.  Every vertex of the live list
+//                   L_{k-1} whose current degree is <= T_k fails: its
+//                   removed_at is set to k and its bit in the live bitmap is
+//                   cleared.  Each tile of the live list records how many of
+//                   its vertices fail with degree > 0, how many survive, the
+//                   total CSR row length of the former and the sum of the
+//                   current degrees of all failures.
+//   k_scan_tiles    exclusive prefix of the tile counts (one workgroup).
+//   k_mark_scatter  compacts, in live-list order, the survivors into L_k and
+//                   the failures with degree > 0 into the walk list, together
+//                   with the exclusive prefix of their row lengths and, for
+//                   every walk tile, the walk-list index that owns its first
+//                   adjacency entry.
+//   k_walk          part 2, the neighbour walk.  The adjacency entries of the
+//                   walk list form one flat range that is cut into equal
+//                   tiles, so hub rows are spread over many workgroups.  A
+//                   neighbour still in the graph loses one degree (device
+//                   atomic); entries into vertices that failed in this or an
+//                   earlier pass are skipped.  The last workgroup to finish
+//                   reduces |V| and |E|, keeps the best graph, and derives
+//                   the threshold of the next pass.
+//
+// The "barrier synchronization" between the two parts of Algorithm 1 is the
+// kernel boundary between k_mark_scatter and k_walk.
+//
+// Exact integer arithmetic makes every result independent of launch shape
+// and atomic order.  The failure test deg * |V| * den <= 2(num+den)|E| is
+// evaluated as deg <= T_k with T_k = floor(2(num+den)|E| / (|V| den)), which
+// is the same test for integer deg.  The number of entries between two
+// vertices that fail together is not counted explicitly: every failed vertex
+// of current degree d has exactly d entries into the graph of the pass start,
+// so intra = sum(d) - cross, and |E| drops by cross + intra / 2.
+//
+// Vertices that fail with degree 0 have no neighbour left in the graph; their
+// rows are not walked.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+#include "dsg.h"
+
+namespace dsg {
+
+// Pointers into one workspace allocation.
+struct Work {
+    DevState* st;
+    int32_t* deg;         // n: current degree of every vertex still present
+    int32_t* removed_at;  // n: pass of failure, kNever while present
+    uint32_t* live;       // ceil(n/32): bit v set while v is present
+    int32_t* list0;       // n: live lists of even passes
+    int32_t* list1;       // n: live lists of odd passes (and of pass 1's output)
+    int32_t* alist;       // n: walk list of the current pass
+    int32_t* aoff;        // n+1: exclusive prefix of the walk list's row lengths
+    int32_t* tile_first;  // walk tiles + 1: walk-list index owning each tile start
+    int4* tiles;          // mark tiles + 1: per-tile counts, then their prefix
+    PassRecord* trace;    // kTraceCap
+};
+
+static_assert(sizeof(PassRecord) == sizeof(dsg_pass_trace), "trace layout");
+
+__device__ inline const int32_t* live_in(const Work& w, int32_t pass) {
+    return pass == 1 ? nullptr : ((pass - 1) & 1 ? w.list1 : w.list0);
+}
+__device__ inline int32_t* live_out(const Work& w, int32_t pass) {
+    return (pass & 1) ? w.list1 : w.list0;
+}
+
+// ------------------------------------------------------------------ init
+// Two kernels so that the per-vertex kernel can flag a bad row_ptr without
+// racing the initialisation of the state.
+
+__global__ void k_init_state(Work w, const int32_t* __restrict__ rp, int64_t n, int64_t m,
+                             int64_t num, int64_t den, int32_t max_pass, int32_t trace_cap) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    DevState* st = w.st;
+    st->S = n;
+    st->E = m;
+    st->best_E = m;
+    st->best_S = n;
+    st->eps_num = num;
+    st->eps_den = den;
+    st->nA = st->nL = st->edges = st->sumdeg = 0;
+    st->cross = 0;
+    st->best_count = 0;
+    st->tot_walked = st->tot_cross = st->tot_live = st->tot_alist = 0;
+    st->pass = 1;
+    st->T = pass_threshold(m, n, num, den);
+    st->best_pass = 0;
+    st->done = 0;
+    st->status = kStOk;
+    st->ticket = 0;
+    st->max_pass = max_pass;
+    st->trace_cap = trace_cap;
+    st->n_tiles_walk = 0;
+    if (rp[0] != 0 || (int64_t)rp[n] != 2 * m) {
+        st->status = kStBadRowPtr;
+        st->done = 1;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_init(Work w, const int32_t* __restrict__ rp,
+                                                 int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    bool bad = false;
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += stride) {
+        const int32_t d = rp[v + 1] - rp[v];
+        bad |= d < 0;
+        w.deg[v] = d;
+        w.removed_at[v] = kNever;
+    }
+    const int64_t nw = (n + 31) >> 5;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nw; i += stride) {
+        const int64_t left = n - i * 32;
+        w.live[i] = left >= 32 ? 0xFFFFFFFFu : ((1u << left) - 1u);
+    }
+    if (bad) {
+        // every writer stores the same values; later kernels see them
+        w.st->status = kStBadRowPtr;
+        w.st->done = 1;
+    }
+}
+
+// ------------------------------------------------------------ mark: count
+
+__global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __restrict__ rp,
+                                                       int64_t n) {
+    const DevState* st = w.st;
+    if (st->done) return;
+    const int32_t pass = st->pass;
+    const int64_t S = st->S;
+    const int32_t T = st->T;
+    const int32_t* __restrict__ lin = live_in(w, pass);
+    const int64_t ntiles = (S + kMarkTile - 1) / kMarkTile;
+    __shared__ uint32_t red[kWaves];
+
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t base = t * kMarkTile + (int64_t)threadIdx.x * kMarkItems;
+        uint32_t cA = 0, cL = 0, cE = 0, cD = 0;
+        uint32_t wi = 0xFFFFFFFFu, wm = 0;
+#pragma unroll
+        for (int j = 0; j < kMarkItems; ++j) {
+            const int64_t idx = base + j;
+            const int32_t v = idx < S ? (lin ? lin[idx] : (int32_t)idx) : -1;
+            if ((uint64_t)(int64_t)v < (uint64_t)n) {
+                const int32_t d = w.deg[v];
+                if (d <= T) {
+                    w.removed_at[v] = pass;
+                    const uint32_t word = (uint32_t)v >> 5;
+                    if (word != wi) {
+                        if (wm) atomicAnd(&w.live[wi], ~wm);
+                        wi = word;
+                        wm = 0;
+                    }
+                    wm |= 1u << (v & 31);
+                    if (d > 0) {
+                        ++cA;
+                        cE += (uint32_t)(rp[v + 1] - rp[v]);
+                        cD += (uint32_t)d;
+                    }
+                } else {
+                    ++cL;
+                }
+            }
+        }
+        if (wm) atomicAnd(&w.live[wi], ~wm);
+        const uint32_t tA = block_sum(cA, red);
+        const uint32_t tL = block_sum(cL, red);
+        const uint32_t tE = block_sum(cE, red);
+        const uint32_t tD = block_sum(cD, red);
+        if (threadIdx.x == 0) w.tiles[t] = make_int4((int)tA, (int)tL, (int)tE, (int)tD);
+    }
+}
+
+// ---------------------------------------------------- prefix of tile counts
+// mode 0: the tiles of the current pass's live list (components A, L, E; D
+//         summed only).  mode 1: the extract tiles over 0..n-1 (component A).
+
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(Work w, int32_t mode, int64_t n) {
+    DevState* st = w.st;
+    if (mode == 0) {
+        if (st->done) return;
+    } else {
+        if (!st->done || st->status != kStOk) return;
+    }
+    const int64_t items = mode == 0 ? st->S : n;
+    const int64_t nt = (items + kMarkTile - 1) / kMarkTile;
+    const int64_t per = (nt + kBlock - 1) / kBlock;
+    const int64_t lo = std::min<int64_t>(nt, per * threadIdx.x);
+    const int64_t hi = std::min<int64_t>(nt, lo + per);
+    int64_t a = 0, l = 0, e = 0, d = 0;
+    for (int64_t i = lo; i < hi; ++i) {
+        const int4 c = w.tiles[i];
+        a += c.x;
+        l += c.y;
+        e += (uint32_t)c.z;
+        d += (uint32_t)c.w;
+    }
+    __shared__ int64_t red[kWaves];
+    int64_t ta, tl, te;
+    int64_t pa = block_excl_sum(a, red, &ta);
+    int64_t pl = block_excl_sum(l, red, &tl);
+    int64_t pe = block_excl_sum(e, red, &te);
+    const int64_t td = block_sum(d, red);
+    for (int64_t i = lo; i < hi; ++i) {
+        const int4 c = w.tiles[i];
+        w.tiles[i] = make_int4((int)pa, (int)pl, (int)pe, c.w);
+        pa += c.x;
+        pl += c.y;
+        pe += (uint32_t)c.z;
+    }
+    if (threadIdx.x == 0) {
+        if (mode == 0) {
+            st->nA = ta;
+            st->nL = tl;
+            st->edges = te;
+            st->sumdeg = td;
+            st->n_tiles_walk = (int32_t)((te + kWalkTile - 1) / kWalkTile);
+            st->tot_live += items;
+            st->tot_alist += ta;
+            st->cross = 0;
+            st->ticket = 0;
+            w.aoff[ta] = (int32_t)te;
+        } else {
+            st->best_count = ta;
+        }
+    }
+}
+
+// ---------------------------------------------------------- mark: scatter
+
+__global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* __restrict__ rp,
+                                                         int64_t n, int64_t walk_cap) {
+    const DevState* st = w.st;
+    if (st->done) return;
+    const int32_t pass = st->pass;
+    const int64_t S = st->S;
+    const int32_t T = st->T;
+    const int32_t* __restrict__ lin = live_in(w, pass);
+    int32_t* __restrict__ lout = live_out(w, pass);
+    const int64_t ntiles = (S + kMarkTile - 1) / kMarkTile;
+    __shared__ uint32_t red[kWaves];
+
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t base = t * kMarkTile + (int64_t)threadIdx.x * kMarkItems;
+        int32_t vv[kMarkItems];
+        int32_t dd[kMarkItems];
+        int32_t ll[kMarkItems];
+        uint32_t cA = 0, cL = 0, cE = 0;
+#pragma unroll
+        for (int j = 0; j < kMarkItems; ++j) {
+            const int64_t idx = base + j;
+            vv[j] = -1;
+            dd[j] = 0;
+            ll[j] = 0;
+            const int32_t v = idx < S ? (lin ? lin[idx] : (int32_t)idx) : -1;
+            if ((uint64_t)(int64_t)v < (uint64_t)n) {
+                const int32_t d = w.deg[v];
+                vv[j] = v;
+                dd[j] = d;
+                if (d <= T) {
+                    if (d > 0) {
+                        ll[j] = rp[v + 1] - rp[v];
+                        ++cA;
+                        cE += (uint32_t)ll[j];
+                    }
+                } else {
+                    ++cL;
+                }
+            }
+        }
+        uint32_t tot_packed, tot_e;
+        const uint32_t ex_packed = block_excl_sum(cA | (cL << 16), red, &tot_packed);
+        const uint32_t ex_e = block_excl_sum(cE, red, &tot_e);
+        const int4 tp = w.tiles[t];
+        int64_t pA = (int64_t)tp.x + (ex_packed & 0xFFFFu);
+        int64_t pL = (int64_t)tp.y + (ex_packed >> 16);
+        int64_t pE = (int64_t)(uint32_t)tp.z + ex_e;
+#pragma unroll
+        for (int j = 0; j < kMarkItems; ++j) {
+            const int32_t v = vv[j];
+            if (v < 0) continue;
+            if (dd[j] <= T) {
+                if (dd[j] > 0 && pA < n) {
+                    w.alist[pA] = v;
+                    w.aoff[pA] = (int32_t)pE;
+                    const int64_t len = ll[j];
+                    // walk tiles whose first entry lies in [pE, pE + len)
+                    for (int64_t tt = (pE + kWalkTile - 1) / kWalkTile;
+                         tt * kWalkTile < pE + len && tt < walk_cap; ++tt)
+                        w.tile_first[tt] = (int32_t)pA;
+                    ++pA;
+                    pE += len;
+                }
+            } else if (pL < n) {
+                lout[pL++] = v;
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------- pass completion
+
+__device__ void finish_pass(const Work& w) {
+    DevState* st = w.st;
+    if (st->status != kStOk) {
+        st->done = 1;
+        return;
+    }
+    const int64_t cross = (int64_t)atomic_load_u64(&st->cross);
+    const int64_t S_in = st->S, E_in = st->E;
+    const int64_t S_out = st->nL;
+    const int64_t intra = st->sumdeg - cross;
+    const int32_t pass = st->pass;
+    const int64_t E_out = E_in - cross - intra / 2;
+    if (intra < 0 || (intra & 1) || E_out < 0 || (S_out == 0 && E_out != 0)) {
+        st->status = kStInvariant;
+        st->done = 1;
+        return;
+    }
+    if (pass <= st->trace_cap) {
+        PassRecord r;
+        r.s_in = S_in;
+        r.e_in = E_in;
+        r.thresh = st->T;
+        r.removed = S_in - S_out;
+        r.cross = cross;
+        r.intra = intra;
+        r.walked = st->edges;
+        r.s_out = S_out;
+        r.e_out = E_out;
+        w.trace[pass - 1] = r;
+    }
+    st->tot_walked += st->edges;
+    st->tot_cross += cross;
+    if (S_out > 0 && E_out * st->best_S > st->best_E * S_out) {
+        st->best_E = E_out;
+        st->best_S = S_out;
+        st->best_pass = pass;
+    }
+    st->S = S_out;
+    st->E = E_out;
+    __hip_atomic_store(&st->cross, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (S_out == 0) {
+        st->done = 1;
+        return;
+    }
+    if (pass + 1 > st->max_pass) {
+        st->status = kStWatchdog;
+        st->done = 1;
+        return;
+    }
+    st->T = pass_threshold(E_out, S_out, st->eps_num, st->eps_den);
+    st->pass = pass + 1;
+}
+
+// ------------------------------------------------------------------ walk
+
+__global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ ci, int64_t n,
+                                                 int64_t nnz) {
+    DevState* st = w.st;
+    if (st->done) return;
+    const int64_t nA = st->nA;
+    const int64_t total = st->edges;
+    const int64_t ntiles = st->n_tiles_walk;
+    int32_t* __restrict__ deg = w.deg;
+    const uint32_t* __restrict__ live = w.live;
+
+    __shared__ __align__(16) int32_t own[kWalkTile];
+    __shared__ int32_t bas[kWalkTile + 1];
+    __shared__ int32_t red[kWaves];
+    __shared__ unsigned long long redc[kWaves];
+
+    uint32_t cross = 0;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t e0 = t * kWalkTile;
+        const int32_t len = (int32_t)std::min<int64_t>(kWalkTile, total - e0);
+        const int64_t i0 = w.tile_first[t];
+        const int64_t ihi = (t + 1 < ntiles) ? (int64_t)w.tile_first[t + 1] : nA - 1;
+        if (i0 < 0 || ihi >= nA || ihi < i0 || ihi - i0 + 1 > kWalkTile + 1) {
+            // cannot happen for a consistent walk list; never index with it
+            if (threadIdx.x == 0) w.st->status = kStInvariant;
+            continue;
+        }
+        const int32_t c = (int32_t)(ihi - i0 + 1);
+
+        for (int p = threadIdx.x; p < kWalkTile; p += kBlock) own[p] = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < c; i += kBlock) {
+            const int64_t a = i0 + i;
+            const int32_t off = w.aoff[a];
+            const int32_t v = w.alist[a];
+            bas[i] = rp[v] - off;
+            const int64_t o = (int64_t)off - e0;
+            if (o < len) own[o > 0 ? o : 0] = i;
+        }
+        __syncthreads();
+        {
+            // inclusive running max of own[] = index of the row owning each entry
+            const int b = threadIdx.x * kWalkItems;
+            int32_t loc[kWalkItems];
+            int32_t run = 0;
+#pragma unroll
+            for (int j = 0; j < kWalkItems; ++j) {
+                run = max(run, own[b + j]);
+                loc[j] = run;
+            }
+            const int32_t carry = block_excl_max(run, red, 0);
+#pragma unroll
+            for (int j = 0; j < kWalkItems; ++j) own[b + j] = max(loc[j], carry);
+        }
+        __syncthreads();
+        int32_t u[kWalkItems];
+#pragma unroll
+        for (int j = 0; j < kWalkItems; ++j) {
+            const int p = j * kBlock + threadIdx.x;
+            u[j] = -1;
+            if (p < len) {
+                const int64_t pos = (int64_t)bas[own[p]] + e0 + p;
+                if ((uint64_t)pos < (uint64_t)nnz) {
+                    const int32_t x = ci[pos];
+                    u[j] = (int64_t)(uint32_t)x < n ? x : -1;  // ids outside 0..n-1 are ignored
+                }
+            }
+        }
+        uint32_t word[kWalkItems];
+#pragma unroll
+        for (int j = 0; j < kWalkItems; ++j) word[j] = u[j] >= 0 ? live[u[j] >> 5] : 0u;
+#pragma unroll
+        for (int j = 0; j < kWalkItems; ++j) {
+            if (u[j] >= 0 && ((word[j] >> (u[j] & 31)) & 1u)) {
+                __hip_atomic_fetch_add(&deg[u[j]], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ++cross;
+            }
+        }
+        __syncthreads();
+    }
+    const unsigned long long bc = block_sum((unsigned long long)cross, redc);
+    if (threadIdx.x == 0) {
+        if (bc) atomicAdd(&st->cross, bc);
+        __threadfence();
+        const uint32_t tk = atomicAdd(&st->ticket, 1u);
+        if (tk == gridDim.x - 1) {
+            __threadfence();
+            finish_pass(w);
+        }
+    }
+}
+
+// --------------------------------------------------------------- extract
+// S~ = { v : removed_at[v] > best_pass }, ascending.
+
+__global__ __launch_bounds__(kBlock) void k_extract_count(Work w, int64_t n) {
+    const DevState* st = w.st;
+    if (!st->done || st->status != kStOk) return;
+    const int32_t bp = st->best_pass;
+    const int64_t ntiles = (n + kMarkTile - 1) / kMarkTile;
+    __shared__ uint32_t red[kWaves];
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t base = t * kMarkTile + (int64_t)threadIdx.x * kMarkItems;
+        uint32_t c = 0;
+#pragma unroll
+        for (int j = 0; j < kMarkItems; ++j)
+            if (base + j < n && w.removed_at[base + j] > bp) ++c;
+        const uint32_t tc = block_sum(c, red);
+        if (threadIdx.x == 0) w.tiles[t] = make_int4((int)tc, 0, 0, 0);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_extract_scatter(Work w, int64_t n,
+                                                            int32_t* __restrict__ best) {
+    const DevState* st = w.st;
+    if (!st->done || st->status != kStOk) return;
+    const int32_t bp = st->best_pass;
+    const int64_t ntiles = (n + kMarkTile - 1) / kMarkTile;
+    __shared__ uint32_t red[kWaves];
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t base = t * kMarkTile + (int64_t)threadIdx.x * kMarkItems;
+        uint32_t keep = 0, c = 0;
+#pragma unroll
+        for (int j = 0; j < kMarkItems; ++j)
+            if (base + j < n && w.removed_at[base + j] > bp) {
+                keep |= 1u << j;
+                ++c;
+            }
+        uint32_t tot;
+        const uint32_t ex = block_excl_sum(c, red, &tot);
+        int64_t pos = (int64_t)w.tiles[t].x + ex;
+#pragma unroll
+        for (int j = 0; j < kMarkItems; ++j)
+            if ((keep >> j & 1u) && pos < n) best[pos++] = (int32_t)(base + j);
+    }
+}
+
+// ================================================================== host
+
+namespace {
+
+struct DevInfo {
+    int cus = 0;
+    int walk_blocks_per_cu = 0;
+    bool ready = false;
+};
+
+std::mutex g_info_mu;
+DevInfo g_info[64];
+
+hipError_t device_info(DevInfo* out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_info_mu);
+    DevInfo& di = g_info[dev];
+    if (!di.ready) {
+        int cus = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        int per = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_walk, kBlock, 0);
+        if (e != hipSuccess) return e;
+        di.cus = cus;
+        di.walk_blocks_per_cu = std::max(per, 1);
+        di.ready = true;
+    }
+    *out = di;
+    return hipSuccess;
+}
+
+inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t st, deg, rem, live, l0, l1, alist, aoff, tfirst, tiles, trace, total;
+};
+
+inline int64_t mark_tiles(int64_t n) { return (n + kMarkTile - 1) / kMarkTile + 1; }
+inline int64_t walk_tiles(int64_t m) { return (2 * m + kWalkTile - 1) / kWalkTile + 1; }
+
+Layout layout(int64_t n, int64_t m) {
+    Layout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.st = take(sizeof(DevState));
+    L.deg = take(4 * (size_t)n);
+    L.rem = take(4 * (size_t)n);
+    L.live = take(4 * (size_t)((n + 31) / 32));
+    L.l0 = take(4 * (size_t)n);
+    L.l1 = take(4 * (size_t)n);
+    L.alist = take(4 * (size_t)n);
+    L.aoff = take(4 * (size_t)(n + 1));
+    L.tfirst = take(4 * (size_t)walk_tiles(m));
+    L.tiles = take(sizeof(int4) * (size_t)mark_tiles(n));
+    L.trace = take(sizeof(PassRecord) * (size_t)kTraceCap);
+    L.total = o;
+    return L;
+}
+
+int32_t check_sizes(int64_t n, int64_t m, int64_t num, int64_t den) {
+    if (n < 0 || m < 0 || den < 1 || num < 0) return DSG_EINVAL;
+    if (n > (int64_t)INT32_MAX - 1) return DSG_EOVERFLOW;
+    if (2 * (__int128)m > (__int128)INT32_MAX) return DSG_EOVERFLOW;
+    if (num > INT64_MAX - den) return DSG_EOVERFLOW;
+    const __int128 lim = (__int128)1 << 63;
+    if ((__int128)2 * ((__int128)num + den) * m >= lim) return DSG_EOVERFLOW;
+    if ((__int128)n * den >= lim) return DSG_EOVERFLOW;
+    return DSG_OK;
+}
+
+// Upper bound on the number of passes: every pass of a valid input leaves
+// fewer than |V| / (1 + eps) vertices, so log_{1+eps} n passes plus a margin
+// suffice; with eps = 0 every pass still removes a vertex, so n passes do.
+int32_t pass_bound(int64_t n, int64_t num, int64_t den) {
+    if (n <= 1) return (int32_t)n;
+    if (num == 0) return (int32_t)n;
+    const double k = std::ceil(std::log((double)n) / std::log1p((double)num / (double)den));
+    const double b = std::min((double)n, k + 2.0);
+    return (int32_t)std::max(1.0, b);
+}
+
+int32_t map_hip(hipError_t e) {
+    return e == hipErrorOutOfMemory ? DSG_ENOMEM : DSG_EDEVICE;
+}
+
+thread_local DevState* t_host_state = nullptr;
+
+struct EventLog {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;  // per launch: 0 init, 1 mark, 2 walk, 3 extract
+    bool on = false;
+    hipStream_t s = nullptr;
+    hipError_t begin(int k) {
+        if (!on) return hipSuccess;
+        hipEvent_t a;
+        hipError_t e = hipEventCreate(&a);
+        if (e != hipSuccess) return e;
+        ev.push_back(a);
+        kind.push_back(k);
+        return hipEventRecord(a, s);
+    }
+    hipError_t end() {
+        if (!on) return hipSuccess;
+        hipEvent_t b;
+        hipError_t e = hipEventCreate(&b);
+        if (e != hipSuccess) return e;
+        ev.push_back(b);
+        return hipEventRecord(b, s);
+    }
+    ~EventLog() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace
+
+}  // namespace dsg
+
+using namespace dsg;
+
+#define DSG_HIP(expr)                         \
+    do {                                      \
+        hipError_t _e = (expr);               \
+        if (_e != hipSuccess) {               \
+            rc = map_hip(_e);                 \
+            goto done;                        \
+        }                                     \
+    } while (0)
+
+extern "C" {
+
+int32_t dsg_version(void) { return 1; }
+
+const char* dsg_strerror(int32_t status) {
+    switch (status) {
+        case DSG_OK: return "ok";
+        case DSG_EINVAL: return "invalid argument or input outside the CSR contract";
+        case DSG_EOVERFLOW: return "sizes or eps outside the exact integer range";
+        case DSG_ENOMEM: return "device memory allocation failed";
+        case DSG_EDEVICE: return "HIP runtime error";
+        case DSG_EINTERNAL: return "pass watchdog or edge-count invariant tripped";
+        default: return "unknown status";
+    }
+}
+
+size_t dsg_workspace_bytes(int64_t n, int64_t m) {
+    if (check_sizes(n, m, 0, 1) != DSG_OK) return 0;
+    return layout(n, m).total;
+}
+
+int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_t eps_den,
+                    int32_t* best_ids, int32_t* removed_at, dsg_result* out,
+                    dsg_pass_trace* trace, int32_t trace_cap, const dsg_launch* launch,
+                    dsg_profile* prof, void* workspace, size_t ws_bytes, void* stream) {
+    if (!out || !g) return DSG_EINVAL;
+    int32_t rc = check_sizes(n, m, eps_num, eps_den);
+    if (rc != DSG_OK) return rc;
+    if (n > 0 && !g->row_ptr) return DSG_EINVAL;
+    if (m > 0 && !g->col_idx) return DSG_EINVAL;
+    if (m > 0 && n < 2) return DSG_EINVAL;
+    if (trace_cap < 0 || (trace_cap > 0 && !trace)) return DSG_EINVAL;
+    const Layout L = layout(n, m);
+    if (workspace && ws_bytes < L.total) return DSG_EINVAL;
+    if (workspace && ((uintptr_t)workspace & 255u)) return DSG_EINVAL;
+    if (launch && (launch->mark_grid < 0 || launch->walk_grid < 0 || launch->pass_batch < 0))
+        return DSG_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    if (prof) std::memset(prof, 0, sizeof(*prof));
+    if (n == 0) return DSG_OK;
+
+    hipStream_t s = (hipStream_t)stream;
+    char* base = (char*)workspace;
+    bool owned = false;
+    EventLog log;
+    log.on = prof != nullptr;
+    log.s = s;
+    DevInfo di;
+    Work w;
+    int32_t max_pass, batch;
+    int64_t launched = 0;
+    unsigned mark_grid, walk_grid, init_grid;
+
+    DSG_HIP(device_info(&di));
+    if (!t_host_state) {
+        void* p = nullptr;
+        DSG_HIP(hipHostMalloc(&p, sizeof(DevState), hipHostMallocDefault));
+        t_host_state = (DevState*)p;
+    }
+    if (!base) {
+        DSG_HIP(hipMalloc((void**)&base, L.total));
+        owned = true;
+    }
+    w.st = (DevState*)(base + L.st);
+    w.deg = (int32_t*)(base + L.deg);
+    w.removed_at = removed_at ? removed_at : (int32_t*)(base + L.rem);
+    w.live = (uint32_t*)(base + L.live);
+    w.list0 = (int32_t*)(base + L.l0);
+    w.list1 = (int32_t*)(base + L.l1);
+    w.alist = (int32_t*)(base + L.alist);
+    w.aoff = (int32_t*)(base + L.aoff);
+    w.tile_first = (int32_t*)(base + L.tfirst);
+    w.tiles = (int4*)(base + L.tiles);
+    w.trace = (PassRecord*)(base + L.trace);
+
+    max_pass = pass_bound(n, eps_num, eps_den);
+    {
+        const int64_t mt = mark_tiles(n) - 1;
+        const int64_t wt = std::max<int64_t>(walk_tiles(m) - 1, 1);
+        int64_t mg = launch && launch->mark_grid ? launch->mark_grid : (int64_t)di.cus * 8;
+        int64_t wg = launch && launch->walk_grid ? launch->walk_grid
+                                                 : (int64_t)di.cus * di.walk_blocks_per_cu;
+        mark_grid = (unsigned)std::max<int64_t>(1, std::min(mg, mt));
+        walk_grid = (unsigned)std::max<int64_t>(1, std::min(wg, wt));
+        init_grid = (unsigned)std::max<int64_t>(
+            1, std::min<int64_t>((int64_t)di.cus * 8, (n + kBlock - 1) / kBlock));
+        batch = launch && launch->pass_batch ? launch->pass_batch : std::min(max_pass, 8);
+    }
+
+    DSG_HIP(log.begin(0));
+    k_init_state<<<1, 64, 0, s>>>(w, g->row_ptr, n, m, eps_num, eps_den, max_pass,
+                                  std::min(trace_cap, kTraceCap));
+    k_init<<<init_grid, kBlock, 0, s>>>(w, g->row_ptr, n);
+    DSG_HIP(hipGetLastError());
+    DSG_HIP(log.end());
+
+    for (;;) {
+        for (int32_t b = 0; b < batch; ++b) {
+            DSG_HIP(log.begin(1));
+            k_mark_count<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, n);
+            k_scan_tiles<<<1, kBlock, 0, s>>>(w, 0, n);
+            k_mark_scatter<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, n, walk_tiles(m));
+            DSG_HIP(hipGetLastError());
+            DSG_HIP(log.end());
+            DSG_HIP(log.begin(2));
+            k_walk<<<walk_grid, kBlock, 0, s>>>(w, g->row_ptr, g->col_idx, n, 2 * m);
+            DSG_HIP(hipGetLastError());
+            DSG_HIP(log.end());
+            ++launched;
+        }
+        if (best_ids) {
+            DSG_HIP(log.begin(3));
+            k_extract_count<<<mark_grid, kBlock, 0, s>>>(w, n);
+            k_scan_tiles<<<1, kBlock, 0, s>>>(w, 1, n);
+            k_extract_scatter<<<mark_grid, kBlock, 0, s>>>(w, n, best_ids);
+            DSG_HIP(hipGetLastError());
+            DSG_HIP(log.end());
+        }
+        DSG_HIP(hipMemcpyAsync(t_host_state, w.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        DSG_HIP(hipStreamSynchronize(s));
+        if (t_host_state->done) break;
+        if (launched > (int64_t)max_pass + 1) {
+            rc = DSG_EINTERNAL;
+            goto done;
+        }
+        batch = std::min<int32_t>(batch * 2, 64);
+    }
+    {
+        const DevState& h = *t_host_state;
+        if (h.status == kStBadRowPtr) {
+            rc = DSG_EINVAL;
+            goto done;
+        }
+        if (h.status != kStOk) {
+            rc = DSG_EINTERNAL;
+            goto done;
+        }
+        if (best_ids && h.best_count != h.best_S) {
+            rc = DSG_EINTERNAL;
+            goto done;
+        }
+        out->dens_num = h.best_E;
+        out->dens_den = h.best_S;
+        out->passes = h.pass;
+        out->best_pass = h.best_pass;
+        out->best_size = h.best_S;
+        if (trace && trace_cap > 0) {
+            const int32_t k = std::min(std::min(trace_cap, kTraceCap), h.pass);
+            DSG_HIP(hipMemcpyAsync(trace, w.trace, sizeof(PassRecord) * (size_t)k,
+                                   hipMemcpyDeviceToHost, s));
+            DSG_HIP(hipStreamSynchronize(s));
+        }
+        if (prof) {
+            prof->walked = h.tot_walked;
+            prof->cross = h.tot_cross;
+            prof->live_scanned = h.tot_live;
+            prof->walk_list = h.tot_alist;
+            for (size_t i = 0; i + 1 < log.ev.size(); i += 2) {
+                float ms = 0.f;
+                DSG_HIP(hipEventElapsedTime(&ms, log.ev[i], log.ev[i + 1]));
+                switch (log.kind[i / 2]) {
+                    case 0: prof->ms_init += ms; break;
+                    case 1: prof->ms_mark += ms; prof->launches_mark++; break;
+                    case 2: prof->ms_walk += ms; prof->launches_walk++; break;
+                    default: prof->ms_extract += ms; break;
+                }
+            }
+            if (log.ev.size() >= 2) {
+                float ms = 0.f;
+                DSG_HIP(hipEventElapsedTime(&ms, log.ev.front(), log.ev.back()));
+                prof->ms_total = ms;
+            }
+        }
+    }
+done:
+    if (owned) {
+        // the workspace may still be in use if an error interrupted the stream
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(base);
+    }
+    return rc;
+}
+
+int32_t dsg_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_t eps_den,
+                 int32_t* best_ids, dsg_result* out, void* workspace, size_t ws_bytes,
+                 void* stream) {
+    return dsg_peel_ex(g, n, m, eps_num, eps_den, best_ids, nullptr, out, nullptr, 0, nullptr,
+                       nullptr, workspace, ws_bytes, stream);
+}
+
+}  // extern "C"

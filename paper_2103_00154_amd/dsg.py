@@ -1,0 +1,237 @@
+"""Python binding of libdsg.so (include/dsg.h): argument marshalling only.
+
+Every step of the peel runs in the library's HIP kernels.  torch supplies
+device memory and the current HIP stream.  If the library is missing or fails
+to load, every call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+from pathlib import Path
+
+from . import _build
+
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_P = ctypes.c_void_p
+_SZ = ctypes.c_size_t
+
+DSG_OK = 0
+DSG_EINVAL = -1
+DSG_EOVERFLOW = -2
+DSG_ENOMEM = -3
+DSG_EDEVICE = -4
+DSG_EINTERNAL = -5
+
+#: every symbol include/dsg.h declares
+EXPORTS = ("dsg_version", "dsg_strerror", "dsg_workspace_bytes", "dsg_peel", "dsg_peel_ex",
+           "dsg_validate_csr")
+
+TRACE_FIELDS = ("s_in", "e_in", "thresh", "removed", "cross", "intra", "walked", "s_out", "e_out")
+
+
+class CSR(ctypes.Structure):
+    _fields_ = [("row_ptr", _P), ("col_idx", _P)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("dens_num", _I64), ("dens_den", _I64), ("passes", _I32), ("best_pass", _I32),
+                ("best_size", _I64)]
+
+
+class PassTrace(ctypes.Structure):
+    _fields_ = [(f, _I64) for f in TRACE_FIELDS]
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("mark_grid", _I32), ("walk_grid", _I32), ("pass_batch", _I32),
+                ("reserved", _I32)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("ms_init", ctypes.c_double), ("ms_mark", ctypes.c_double),
+                ("ms_walk", ctypes.c_double), ("ms_extract", ctypes.c_double),
+                ("ms_total", ctypes.c_double), ("launches_walk", _I32),
+                ("launches_mark", _I32), ("walked", _I64), ("cross", _I64),
+                ("live_scanned", _I64), ("walk_list", _I64)]
+
+
+class DsgError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        text = lib().dsg_strerror(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{what}: {text} (status {status})" if what else text)
+        self.status = status
+
+
+_lib = None
+
+
+def library_path() -> Path:
+    return _build.LIB_DSG
+
+
+def lib():
+    """The loaded ctypes handle of libdsg.so (built first if absent)."""
+    global _lib
+    if _lib is None:
+        path = _build.ensure_dsg()
+        try:
+            h = ctypes.CDLL(str(path))
+        except OSError as exc:  # no silent fallback
+            raise RuntimeError(f"cannot load the HIP peeling library {path}: {exc}") from exc
+        h.dsg_version.argtypes = []
+        h.dsg_version.restype = _I32
+        h.dsg_strerror.argtypes = [_I32]
+        h.dsg_strerror.restype = ctypes.c_char_p
+        h.dsg_workspace_bytes.argtypes = [_I64, _I64]
+        h.dsg_workspace_bytes.restype = _SZ
+        h.dsg_peel.argtypes = [ctypes.POINTER(CSR), _I64, _I64, _I64, _I64, _P,
+                               ctypes.POINTER(Result), _P, _SZ, _P]
+        h.dsg_peel.restype = _I32
+        h.dsg_peel_ex.argtypes = [ctypes.POINTER(CSR), _I64, _I64, _I64, _I64, _P, _P,
+                                  ctypes.POINTER(Result), _P, _I32, _P, _P, _P, _SZ, _P]
+        h.dsg_peel_ex.restype = _I32
+        h.dsg_validate_csr.argtypes = [ctypes.POINTER(CSR), _I64, _I64, ctypes.POINTER(_I32), _P]
+        h.dsg_validate_csr.restype = _I32
+        _lib = h
+    return _lib
+
+
+def workspace_bytes(n: int, m: int) -> int:
+    return int(lib().dsg_workspace_bytes(n, m))
+
+
+@dataclass
+class PeelResult:
+    best: object            # torch.int32 device tensor, S~ ascending (None if not extracted)
+    num: int                # |E(S~)|
+    den: int                # |S~|
+    passes: int
+    best_pass: int
+    removed_at: object = None  # torch.int32 device tensor or None
+    trace: list = field(default_factory=list)
+    profile: dict | None = None
+
+    @property
+    def density(self) -> float:
+        return self.num / self.den if self.den else 0.0
+
+
+def _check_int32_cuda(name, t):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int32 or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch.int32 tensor on a HIP device")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def alloc_workspace(n: int, m: int, device=None):
+    """A torch uint8 tensor sized for dsg_peel on a graph with (n, m)."""
+    import torch
+    nbytes = workspace_bytes(n, m)
+    if nbytes == 0:
+        raise DsgError(DSG_EINVAL, "workspace_bytes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
+
+
+def peel(row_ptr, col_idx, eps=(1, 10), *, m: int | None = None, extract: bool = True,
+         best_ids=None, removed_at: bool | object = False, trace: bool = False, workspace=None,
+         launch: dict | None = None, profile: bool = False, stream=None) -> PeelResult:
+    """Peel the graph (row_ptr, col_idx) with eps = eps[0] / eps[1].
+
+    row_ptr, col_idx: contiguous torch.int32 tensors on the current HIP device.
+    m defaults to len(col_idx) // 2.  ``removed_at=True`` returns the pass in
+    which each vertex failed (or pass a preallocated int32[n] tensor).
+    ``workspace`` is an optional uint8 device tensor of at least
+    :func:`workspace_bytes` bytes; without it the library allocates one.
+    """
+    import torch
+    _check_int32_cuda("row_ptr", row_ptr)
+    _check_int32_cuda("col_idx", col_idx)
+    n = row_ptr.numel() - 1
+    if n < 0:
+        raise ValueError("row_ptr needs n+1 entries")
+    if m is None:
+        m = col_idx.numel() // 2
+    num, den = int(eps[0]), int(eps[1])
+    dev = row_ptr.device
+    h = lib()
+    csr = CSR(row_ptr.data_ptr(), col_idx.data_ptr() if col_idx.numel() else None)
+    best = None
+    if extract:
+        if best_ids is not None:
+            _check_int32_cuda("best_ids", best_ids)
+            if best_ids.numel() < n:
+                raise ValueError("best_ids needs room for n ids")
+            best = best_ids
+        else:
+            best = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    rem = None
+    if removed_at is True:
+        rem = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    elif removed_at is not False and removed_at is not None:
+        _check_int32_cuda("removed_at", removed_at)
+        if removed_at.numel() < n:
+            raise ValueError("removed_at needs n entries")
+        rem = removed_at
+    ws_ptr, ws_len = None, 0
+    if workspace is not None:
+        if not workspace.is_cuda:
+            raise TypeError("workspace must be device memory")
+        ws_ptr, ws_len = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    cap = (n + 1) if trace else 0
+    cap = min(cap, 4096)
+    tr = (PassTrace * max(cap, 1))()
+    ln = None
+    if launch:
+        ln = Launch(int(launch.get("mark_grid", 0)), int(launch.get("walk_grid", 0)),
+                    int(launch.get("pass_batch", 0)), 0)
+    prof = Profile() if profile else None
+    res = Result()
+    with torch.cuda.device(dev):
+        rc = h.dsg_peel_ex(ctypes.byref(csr), n, m, num, den,
+                           best.data_ptr() if best is not None else None,
+                           rem.data_ptr() if rem is not None else None, ctypes.byref(res),
+                           ctypes.addressof(tr) if cap else None, cap,
+                           ctypes.byref(ln) if ln is not None else None,
+                           ctypes.byref(prof) if prof is not None else None,
+                           ws_ptr, ws_len, _stream_handle(stream))
+    if rc != DSG_OK:
+        raise DsgError(rc, "dsg_peel_ex")
+    passes = []
+    for k in range(min(res.passes, cap)):
+        passes.append({f: int(getattr(tr[k], f)) for f in TRACE_FIELDS})
+    pd = None
+    if prof is not None:
+        pd = {f: getattr(prof, f) for f, _ in Profile._fields_}
+    return PeelResult(best=best[:res.best_size] if best is not None else None,
+                      num=res.dens_num, den=res.dens_den, passes=res.passes,
+                      best_pass=res.best_pass,
+                      removed_at=rem[:n] if rem is not None else None, trace=passes, profile=pd)
+
+
+def validate_csr(row_ptr, col_idx, m: int | None = None, stream=None) -> int:
+    """0 if the device CSR meets the input contract, else the violated rule
+    number (see include/dsg.h)."""
+    import torch
+    _check_int32_cuda("row_ptr", row_ptr)
+    _check_int32_cuda("col_idx", col_idx)
+    n = row_ptr.numel() - 1
+    m = col_idx.numel() // 2 if m is None else m
+    csr = CSR(row_ptr.data_ptr(), col_idx.data_ptr() if col_idx.numel() else None)
+    detail = _I32(0)
+    with torch.cuda.device(row_ptr.device):
+        rc = lib().dsg_validate_csr(ctypes.byref(csr), n, m, ctypes.byref(detail),
+                                    _stream_handle(stream))
+    if rc == DSG_EINVAL and detail.value:
+        return int(detail.value)
+    if rc != DSG_OK:
+        raise DsgError(rc, "dsg_validate_csr")
+    return 0

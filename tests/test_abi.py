@@ -1,0 +1,130 @@
+"""The C ABI of libdsg.so on the CPU: the library loads, exports every
+symbol include/dsg.h declares, its structs match the ctypes mirrors, and
+argument checks return their documented status before any HIP call."""
+from __future__ import annotations
+
+import ctypes
+import re
+import subprocess
+from pathlib import Path
+
+import pytest
+
+from paper_2103_00154_amd import _build, dsg
+
+ROOT = Path(__file__).resolve().parents[1]
+HEADER = ROOT / "include" / "dsg.h"
+
+
+def _declared():
+    text = re.sub(r"/\*.*?\*/", "", HEADER.read_text(), flags=re.S)
+    return sorted(set(re.findall(r"\b(dsg_\w+)\s*\(", text)))
+
+
+def test_header_declarations_match_binding():
+    assert _declared() == sorted(dsg.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    h = dsg.lib()
+    for name in _declared():
+        assert hasattr(h, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", str(_build.LIB_DSG)],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (dsg_\w+)", out))
+    assert set(_declared()) <= exported
+
+
+def test_version_and_strerror():
+    h = dsg.lib()
+    assert h.dsg_version() == 1
+    for code in (0, -1, -2, -3, -4, -5, -99):
+        assert h.dsg_strerror(code)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    src = tmp_path / "sizes.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "dsg.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\","
+        "sizeof(dsg_csr), sizeof(dsg_result), sizeof(dsg_pass_trace), sizeof(dsg_launch),"
+        "sizeof(dsg_profile), offsetof(dsg_result, best_size), offsetof(dsg_profile, walked));"
+        "return 0;}\n")
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-std=c11", f"-I{ROOT / 'include'}", str(src), "-o", str(exe)],
+                   check=True)
+    got = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True,
+                                       check=True).stdout.split()))
+    want = [ctypes.sizeof(dsg.CSR), ctypes.sizeof(dsg.Result), ctypes.sizeof(dsg.PassTrace),
+            ctypes.sizeof(dsg.Launch), ctypes.sizeof(dsg.Profile), dsg.Result.best_size.offset,
+            dsg.Profile.walked.offset]
+    assert got == want
+
+
+def test_workspace_bytes():
+    h = dsg.lib()
+    small = h.dsg_workspace_bytes(1000, 5000)
+    big = h.dsg_workspace_bytes(1 << 24, 261_000_000)
+    assert 24 * 1000 <= small < 24 * 1000 + 1_000_000
+    assert 24 * (1 << 24) <= big < 25 * (1 << 24) + 2_000_000
+    assert h.dsg_workspace_bytes(-1, 0) == 0
+    assert h.dsg_workspace_bytes(2**31, 0) == 0
+    assert h.dsg_workspace_bytes(10, 2**30) == 0
+
+
+def _call(n, m, num, den, rp=0x1000, ci=0x2000, best=0x3000, out=True, ws=None, ws_len=0,
+          trace_cap=0, trace=None):
+    h = dsg.lib()
+    csr = dsg.CSR(rp, ci)
+    res = dsg.Result()
+    return h.dsg_peel_ex(ctypes.byref(csr), n, m, num, den, best, None,
+                         ctypes.byref(res) if out else None, trace, trace_cap, None, None, ws,
+                         ws_len, None), res
+
+
+# Every case below is rejected by the host checks before the library makes
+# any HIP call (the pointers are never dereferenced), so it runs without a GPU.
+@pytest.mark.parametrize("args,status", [
+    (dict(n=-1, m=0, num=1, den=10), dsg.DSG_EINVAL),
+    (dict(n=5, m=-1, num=1, den=10), dsg.DSG_EINVAL),
+    (dict(n=5, m=2, num=1, den=0), dsg.DSG_EINVAL),
+    (dict(n=5, m=2, num=-1, den=10), dsg.DSG_EINVAL),
+    (dict(n=5, m=2, num=1, den=10, out=False), dsg.DSG_EINVAL),
+    (dict(n=5, m=2, num=1, den=10, rp=None), dsg.DSG_EINVAL),
+    (dict(n=5, m=2, num=1, den=10, ci=None), dsg.DSG_EINVAL),
+    (dict(n=1, m=1, num=1, den=10), dsg.DSG_EINVAL),
+    (dict(n=5, m=2, num=1, den=10, ws=0x10000, ws_len=64), dsg.DSG_EINVAL),
+    (dict(n=5, m=2, num=1, den=10, ws=0x10001, ws_len=1 << 20), dsg.DSG_EINVAL),
+    (dict(n=5, m=2, num=1, den=10, trace_cap=4, trace=None), dsg.DSG_EINVAL),
+    (dict(n=5, m=2, num=1, den=10, trace_cap=-1), dsg.DSG_EINVAL),
+    (dict(n=2**31, m=1, num=1, den=10), dsg.DSG_EOVERFLOW),
+    (dict(n=10, m=2**30, num=1, den=10), dsg.DSG_EOVERFLOW),
+    (dict(n=100, m=1 << 29, num=1 << 33, den=1), dsg.DSG_EOVERFLOW),
+    (dict(n=1 << 30, m=10, num=1, den=1 << 40), dsg.DSG_EOVERFLOW),
+    (dict(n=5, m=2, num=2**63 - 5, den=10), dsg.DSG_EOVERFLOW),
+])
+def test_argument_errors_before_device_work(args, status):
+    rc, _ = _call(**args)
+    assert rc == status
+
+
+def test_empty_graph_needs_no_device():
+    rc, res = _call(n=0, m=0, num=1, den=10, rp=None, ci=None, best=None)
+    assert rc == dsg.DSG_OK
+    assert (res.passes, res.best_pass, res.dens_num, res.dens_den, res.best_size) == (0, 0, 0, 0, 0)
+
+
+def test_validate_rejects_bad_arguments_on_host():
+    h = dsg.lib()
+    csr = dsg.CSR(None, None)
+    d = ctypes.c_int32(0)
+    assert h.dsg_validate_csr(ctypes.byref(csr), 5, 0, ctypes.byref(d), None) == dsg.DSG_EINVAL
+    assert h.dsg_validate_csr(None, 5, 0, ctypes.byref(d), None) == dsg.DSG_EINVAL
+    assert h.dsg_validate_csr(ctypes.byref(csr), 0, 0, ctypes.byref(d), None) == dsg.DSG_OK
+
+
+def test_package_has_no_cpu_fallback():
+    src = (ROOT / "paper_2103_00154_amd" / "dsg.py").read_text()
+    assert "oracle" not in src
+    for path in (ROOT / "paper_2103_00154_amd").rglob("*.py"):
+        assert "import oracle" not in path.read_text(), path

@@ -1,0 +1,211 @@
+"""Bit-exact parity of the HIP peeling path with the CPU oracle.
+
+Every comparison covers the best set, the density numerator and
+denominator, the pass count, the best pass, the removal pass of every vertex
+and the per-pass trace (|V|, |E|, threshold, removed, cross and intra
+entries).  Integer work, so the tolerance is zero.
+"""
+from __future__ import annotations
+
+import itertools
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_same, check, say, to_device
+from paper_2103_00154_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+EPS = [(0, 1), (1, 100), (1, 10), (1, 2), (1, 1), (3, 1)]
+
+
+@pytest.fixture(scope="module")
+def dsg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2103_00154_amd import dsg as mod
+    mod.lib()
+    return mod
+
+
+def test_golden_cases_on_gpu(dsg, golden):
+    for case in golden:
+        g = inputs.from_edges(case["n"], case["edges"], name=case["name"])
+        if g.n == 0:
+            continue
+        r, _ = check(g, case["eps"])
+        x = case["expect"]
+        assert (r.passes, r.best_pass, r.num, r.den) == (
+            x["passes"], x["best_pass"], x["num"], x["den"]), case["name"]
+        assert r.best.cpu().tolist() == x["best"], case["name"]
+
+
+def test_exhaustive_graphs_up_to_four_vertices(dsg):
+    for n in range(1, 5):
+        pairs = list(itertools.combinations(range(n), 2))
+        for mask in range(1 << len(pairs)):
+            g = inputs.from_edges(n, [p for i, p in enumerate(pairs) if mask >> i & 1])
+            for e in EPS:
+                rp, ci = to_device(g)
+                r = dsg.peel(rp, ci, e, removed_at=True, trace=True)
+                assert_same(r, oracle.peel_graph(g, *e), n)
+
+
+def test_sampled_small_graphs(dsg):
+    rnd = random.Random(11)
+    for _ in range(150):
+        n = rnd.randint(5, 40)
+        g = inputs.random_small(n, rnd.choice([0.05, 0.2, 0.5, 0.9]), rnd.getrandbits(30))
+        e = rnd.choice(EPS)
+        rp, ci = to_device(g)
+        r = dsg.peel(rp, ci, e, removed_at=True, trace=True)
+        assert_same(r, oracle.peel_graph(g, *e), n)
+
+
+def _tile_edge_graphs():
+    # sizes straddle the 2048-entry mark and walk tiles and leave ragged tails
+    yield inputs.erdos_renyi(2047, 3000, 1)
+    yield inputs.erdos_renyi(2048, 1024, 2)
+    yield inputs.erdos_renyi(2049, 8191, 3)
+    yield inputs.erdos_renyi(4097, 20480, 4)
+    yield inputs.chung_lu(50001, 12, 2.1, 5)
+    yield inputs.chung_lu(30000, 40, 2.6, 6)
+    yield inputs.rmat(15, 16, seed=7)
+    yield inputs.rmat(14, 8, seed=8, planted=(300, 0.4, 9))
+    yield inputs.star(100_000)
+    yield inputs.path(20_001)
+    yield inputs.disjoint_cliques(90, 50)
+    yield inputs.empty(5000)
+    yield inputs.clique(300)
+
+
+@pytest.mark.parametrize("gi", range(13))
+def test_families_across_tile_boundaries(dsg, gi):
+    g = list(_tile_edge_graphs())[gi]
+    for e in [(0, 1), (1, 10), (1, 1)]:
+        check(g, e)
+
+
+def test_config_small_er(dsg):
+    """Erdos-Renyi n=10,000, m=50,000, seed 0, eps=1/10."""
+    g = inputs.erdos_renyi(10_000, 50_000, 0)
+    r, o = check(g, (1, 10))
+    assert r.best.numel() == o.den
+
+
+@pytest.mark.parametrize("eps", [(1, 100), (1, 10), (1, 1)])
+def test_config_rmat20(dsg, eps):
+    """R-MAT scale 20, edge factor 16, (a,b,c,d) = (.57,.19,.19,.05)."""
+    g = _rmat20()
+    check(g, eps)
+
+
+_cache = {}
+
+
+def _rmat20():
+    if "r20" not in _cache:
+        _cache["r20"] = inputs.rmat(20, 16, seed=0)
+    return _cache["r20"]
+
+
+@pytest.mark.parametrize("launch", [
+    {"walk_grid": 1}, {"walk_grid": 3, "mark_grid": 1}, {"walk_grid": 64, "mark_grid": 7},
+    {"pass_batch": 1}, {"pass_batch": 2, "walk_grid": 1000}, {"mark_grid": 5000},
+])
+def test_launch_shape_does_not_change_results(dsg, launch):
+    g = inputs.chung_lu(200_000, 24, 2.2, 12)
+    check(g, (1, 10), launch=launch)
+
+
+def test_relabel_permutes_result(dsg):
+    g = inputs.chung_lu(40_000, 16, 2.3, 13)
+    perm = np.random.default_rng(3).permutation(g.n)
+    h = inputs.relabel(g, perm)
+    ra, _ = check(g, (1, 10))
+    rb, _ = check(h, (1, 10))
+    assert (ra.passes, ra.best_pass, ra.num, ra.den) == (rb.passes, rb.best_pass, rb.num, rb.den)
+    assert sorted(perm[ra.best.cpu().numpy()].tolist()) == rb.best.cpu().tolist()
+
+
+def test_workspace_reuse_and_streams(dsg):
+    import torch
+    big = inputs.rmat(16, 16, seed=21)
+    small = inputs.erdos_renyi(3000, 7000, 22)
+    ws = dsg.alloc_workspace(big.n, big.m)
+    s = torch.cuda.Stream()
+    for g in (big, small, big, small):
+        rp, ci = to_device(g)
+        with torch.cuda.stream(s):
+            r = dsg.peel(rp, ci, (1, 10), removed_at=True, trace=True, workspace=ws)
+        s.synchronize()
+        assert_same(r, oracle.peel_graph(g, 1, 10), g.n)
+    with pytest.raises(dsg.DsgError):
+        rp, ci = to_device(big)
+        dsg.peel(rp, ci, (1, 10), workspace=ws[:1024])
+
+
+def test_without_extraction(dsg):
+    g = inputs.chung_lu(20_000, 10, 2.4, 31)
+    rp, ci = to_device(g)
+    r = dsg.peel(rp, ci, (1, 10), extract=False)
+    o = oracle.peel_graph(g, 1, 10)
+    assert r.best is None
+    assert (r.passes, r.best_pass, r.num, r.den) == (o.passes, o.best_pass, o.num, o.den)
+
+
+def test_repeated_runs_identical(dsg):
+    g = inputs.rmat(16, 16, seed=41)
+    rp, ci = to_device(g)
+    first = dsg.peel(rp, ci, (1, 10), removed_at=True)
+    for _ in range(10):
+        r = dsg.peel(rp, ci, (1, 10), removed_at=True)
+        assert (r.passes, r.best_pass, r.num, r.den) == (
+            first.passes, first.best_pass, first.num, first.den)
+        assert bool((r.removed_at == first.removed_at).all())
+
+
+def test_bad_row_ptr_is_an_error(dsg):
+    import torch
+    g = inputs.erdos_renyi(1000, 3000, 51)
+    rp, ci = to_device(g)
+    with pytest.raises(dsg.DsgError) as exc:  # row_ptr[n] != 2m
+        dsg.peel(rp, ci, (1, 10), m=g.m - 1)
+    assert exc.value.status == dsg.DSG_EINVAL
+    bad = rp.clone()
+    bad[500] = bad[499] - 1  # non-monotone, values stay inside 0..2m
+    with pytest.raises(dsg.DsgError) as exc:
+        dsg.peel(bad, ci, (1, 10))
+    assert exc.value.status == dsg.DSG_EINVAL
+    torch.cuda.synchronize()
+
+
+def test_validate_csr_rules(dsg):
+    import torch
+    g = inputs.rmat(12, 8, seed=61)
+    rp, ci = to_device(g)
+    assert dsg.validate_csr(rp, ci) == 0
+    # missing reverse edge: the last neighbour of v becomes a larger id that
+    # is not adjacent to v (the row stays ascending)
+    deg = g.degrees()
+    v = next(x for x in range(g.n)
+             if deg[x] > 0 and g.col_idx[g.row_ptr[x + 1] - 1] < g.n - 2)
+    last = int(g.col_idx[g.row_ptr[v + 1] - 1])
+    c2 = g.col_idx.copy()
+    c2[g.row_ptr[v + 1] - 1] = last + 1 if last + 1 != v else last + 2
+    assert dsg.validate_csr(rp, torch.from_numpy(c2).cuda()) == 7
+    c3 = g.col_idx.copy()
+    c3[g.row_ptr[v]] = v  # self loop (row 0 stays sorted only if v is smallest)
+    assert dsg.validate_csr(rp, torch.from_numpy(c3).cuda()) in (5, 6, 7)
+    c4 = g.col_idx.copy()
+    c4[0] = g.n + 5  # out of range
+    assert dsg.validate_csr(rp, torch.from_numpy(c4).cuda()) == 4
+    r5 = rp.clone()
+    r5[-1] += 2
+    assert dsg.validate_csr(r5, ci) == 3
+    r6 = rp.clone()
+    r6[10] = r6[9] - 1
+    assert dsg.validate_csr(r6, ci) == 2
