@@ -116,7 +116,7 @@ def main() -> int:
         r = dsg.peel(rp, ci, (num, den), best_ids=best, workspace=ws)
     torch.cuda.synchronize()
 
-    walk_ms = 0.0
+    walk_ms = apply_ms = mark_ms = 0.0
     walk_launches = 0
     walked = cross = walk_list = live = 0
     torch.cuda.synchronize()
@@ -125,6 +125,8 @@ def main() -> int:
         r = dsg.peel(rp, ci, (num, den), best_ids=best, workspace=ws, profile=True)
         p = r.profile
         walk_ms += p["ms_walk"]
+        apply_ms += p["ms_apply"]
+        mark_ms += p["ms_mark"]
         walk_launches += p["launches_walk"]
         walked += p["walked"]
         cross += p["cross"]
@@ -135,20 +137,22 @@ def main() -> int:
     ms_per_step = (t_end - t_start) * 1e3 / args.steps
     gteps = g.m / (ms_per_step * 1e-3) / 1e9
     log(f"GPU: {ms_per_step:.3f} ms/step, {gteps:.1f} GTEPS, passes={r.passes} "
-        f"best={r.num}/{r.den} (pass {r.best_pass})")
+        f"best={r.num}/{r.den} (pass {r.best_pass}); per step: walk {walk_ms / args.steps:.3f} "
+        f"ms, apply {apply_ms / args.steps:.3f} ms, mark {mark_ms / args.steps:.3f} ms")
 
-    # walk kernel: algorithmic bytes = 4 B column id + 4 B neighbour state per
-    # walked entry, 8 B read-modify-write per degree decrement, and 12 B per
-    # walk-list row (id, prefix offset, row start)
-    walk_bytes = 8 * walked + 8 * cross + 12 * walk_list
+    # neighbour walk (the dominant kernel): algorithmic bytes = 4 B column id
+    # + 4 B neighbour state per walked entry, a 2 B record per degree
+    # decrement, and 12 B per walk-list row (id, prefix offset, row start)
+    walk_bytes = 8 * walked + 2 * cross + 12 * walk_list
     per_launch_bytes = walk_bytes / walk_launches
     per_launch_ms = walk_ms / walk_launches
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
     traffic = stored_traffic(args.workload, walk_launches // args.steps)
-    # whole path: walk bytes plus 12 B per live-list test (id, degree,
-    # re-write) and 24 B per vertex (row_ptr pair, init writes, removal pass,
-    # extraction read)
-    path_bytes = (walk_bytes + 12 * live) / args.steps + 24 * g.n
+    # whole path per step, per unit of work: 8 B per walked entry, 8 B per
+    # degree decrement (record written and read, counter update), 12 B per
+    # live-list test (id, degree, re-write), 12 B per walk-list row and 24 B
+    # per vertex (row_ptr pair, removal pass, extraction read, init writes)
+    path_bytes = (8 * walked + 8 * cross + 12 * live + 12 * walk_list) / args.steps + 24 * g.n
     path_gbs = path_bytes / (ms_per_step * 1e-3) / 1e9
 
     cpu = None
@@ -193,6 +197,9 @@ def main() -> int:
                      "launches_per_step": walk_launches // args.steps,
                      "ms_per_launch": round(per_launch_ms, 4),
                      "alg_bytes_per_launch": int(per_launch_bytes)},
+        "kernel_ms_per_step": {"walk": round(walk_ms / args.steps, 4),
+                               "apply": round(apply_ms / args.steps, 4),
+                               "mark": round(mark_ms / args.steps, 4)},
         "path_roofline": {"achieved": round(path_gbs, 1), "unit": "GB/s",
                           "frac": round(path_gbs / HBM_PEAK_GBS, 4),
                           "alg_bytes_per_step": int(path_bytes)},

@@ -94,20 +94,23 @@ typedef struct {
 } dsg_launch;
 
 /* Optional per-kernel timing, measured with HIP events on the call's stream
- * around every launch of the call (host struct, filled on return). */
+ * around every launch of the call (host struct, filled on return).  Launches
+ * enqueued after the last pass return at once and are counted too. */
 typedef struct {
-    double ms_init;     /* init kernel */
+    double ms_init;     /* init kernels */
     double ms_mark;     /* mark-count + tile-scan + mark-scatter kernels */
-    double ms_walk;     /* neighbour-walk kernels (the dominant kernel) */
+    double ms_walk;     /* neighbour-walk kernels */
+    double ms_apply;    /* degree-update kernels (per-bin LDS counts) */
     double ms_extract;  /* extract kernels */
     double ms_total;    /* first launch to last kernel end */
-    int32_t launches_walk;  /* walk launches timed (includes no-op launches
-                               enqueued after the last pass) */
+    int32_t launches_walk;
     int32_t launches_mark;
-    int64_t walked;     /* adjacency entries walked over all passes */
-    int64_t cross;      /* degree decrements over all passes */
+    int32_t launches_apply;
+    int32_t reserved;
+    int64_t walked;       /* adjacency entries walked over all passes */
+    int64_t cross;        /* degree decrements over all passes */
     int64_t live_scanned; /* live-list entries tested over all passes */
-    int64_t walk_list;  /* failed vertices whose rows were walked, all passes */
+    int64_t walk_list;    /* failed vertices whose rows were walked, all passes */
 } dsg_profile;
 
 /* Library ABI version (increments on any incompatible change). */
@@ -117,7 +120,9 @@ int32_t dsg_version(void);
 const char* dsg_strerror(int32_t status);
 
 /* Bytes of device workspace dsg_peel needs for a graph with n vertices and
- * m undirected edges; 0 for invalid sizes.  About 24 n bytes. */
+ * m undirected edges; 0 for invalid sizes.  About 28 n + 4 m bytes plus up
+ * to min(n, 32768) * 4 bytes per degree-update work item (at most
+ * n / 32768 + 514 items). */
 size_t dsg_workspace_bytes(int64_t n, int64_t m);
 
 /*

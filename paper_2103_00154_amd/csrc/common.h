@@ -16,6 +16,18 @@ constexpr int kWalkTile = kBlock * kWalkItems;   // adjacency entries per tile
 constexpr int kTraceCap = 4096;                  // device trace records
 constexpr int32_t kNever = INT32_MAX;            // removed_at of a vertex still present
 
+// Survivor-rank bins of the degree update.  A pass's survivors are numbered
+// 0..|S|-1 by their position in the compacted live list; bin b holds ranks
+// [b * kBinWidth, (b + 1) * kBinWidth).  Records in a bin are 16-bit local
+// ranks, and one apply workgroup keeps a whole bin's counters in LDS.
+constexpr int kBinShift = 15;
+constexpr int kBinWidth = 1 << kBinShift;        // 32768 ranks: 128 KB of LDS counters
+constexpr int kNbLds = 1024;                     // bins the walk can stage in LDS
+constexpr int kWaveAggBins = 8;                  // up to this many bins, slots per wave
+constexpr int kApplyBlock = 1024;                // threads of an apply workgroup
+constexpr int64_t kChunkMin = 8192;              // least records per apply work item
+constexpr int64_t kTargetItems = 512;            // apply work items aimed for per pass
+
 // Device status codes (kept in DevState::status; mapped to dsg_status).
 enum : int32_t {
     kStOk = 0,
@@ -39,12 +51,14 @@ struct alignas(256) DevState {
     int64_t nL;         // survivors of this pass
     int64_t edges;      // adjacency entries of the walk list
     int64_t sumdeg;     // sum of the current degrees of all failed vertices
+    int64_t sumdeg_surv;  // sum of the current degrees of the survivors
     unsigned long long cross;  // survivors' degree decrements, summed by walk blocks
     int64_t best_count; // ids written by the extract kernels
     int64_t tot_walked; // statistics over all passes
     int64_t tot_cross;
     int64_t tot_live;
     int64_t tot_alist;
+    int64_t chunk;      // records per apply work item in this pass
     int32_t pass;       // number of the pass being run (1-based)
     int32_t T;          // threshold of the current pass
     int32_t best_pass;
@@ -54,7 +68,11 @@ struct alignas(256) DevState {
     int32_t max_pass;   // watchdog bound
     int32_t trace_cap;  // records the device trace may hold
     int32_t n_tiles_walk;  // walk tiles of the current pass
-    int32_t pad[1];
+    int32_t nbins;      // survivor-rank bins of the current pass
+    int32_t n_items;    // apply work items of the current pass
+    int32_t part_stride;  // ints per partial-count row (min(kBinWidth, n))
+    int32_t max_items;  // capacity of the work-item table
+    int32_t pad[3];
 };
 
 struct PassRecord {

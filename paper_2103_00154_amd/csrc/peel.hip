@@ -1,44 +1,52 @@
 // peel.hip - Bahmani's (2+2eps) peeling passes on gfx950 and the C ABI of
 // libdsg.so (include/dsg.h).
 //
-// One pass of Algorithm 1 (P-Bahmani, Section 3.1) maps onto four kernels
-// that run back to back on the caller's stream:
+// One pass of Algorithm 1 (P-Bahmani, Section 3.1) runs as six kernels on
+// the caller's stream:
 //
-//   k_mark_count    part 1, the failure test.  Every vertex of the live list
-//                   L_{k-1} whose current degree is <= T_k fails: its
-//                   removed_at is set to k and its bit in the live bitmap is
-//                   cleared.  Each tile of the live list records how many of
-//                   its vertices fail with degree > 0, how many survive, the
-//                   total CSR row length of the former and the sum of the
-//                   current degrees of all failures.
-//   k_scan_tiles    exclusive prefix of the tile counts (one workgroup).
-//   k_mark_scatter  compacts, in live-list order, the survivors into L_k and
-//                   the failures with degree > 0 into the walk list, together
-//                   with the exclusive prefix of their row lengths and, for
-//                   every walk tile, the walk-list index that owns its first
-//                   adjacency entry.
+//   k_mark_count    part 1, the failure test, over the live list L_{k-1}
+//                   and its dense degree array: every vertex whose degree is
+//                   <= T_k fails: removed_at = k, live bit cleared.  Per tile of the live list it records the
+//                   failures with degree > 0, the survivors, the CSR row
+//                   length of the former and the degree sums of both groups.
+//   k_scan_tiles    exclusive prefix of the tile records (one workgroup).
+//   k_mark_scatter  compacts, in live-list order, the survivors (id and
+//                   degree) into L_k and the failures with degree > 0 into
+//                   the walk list.  It also writes the rank directory (per
+//                   32-vertex word: live bits and the number of survivors
+//                   before the word) and the start of every survivor-rank
+//                   bin in the record buffer (prefix of survivor degrees).
 //   k_walk          part 2, the neighbour walk.  The adjacency entries of the
-//                   walk list form one flat range that is cut into equal
-//                   tiles, so hub rows are spread over many workgroups.  A
-//                   neighbour still in the graph loses one degree (device
-//                   atomic); entries into vertices that failed in this or an
-//                   earlier pass are skipped.  The last workgroup to finish
-//                   reduces |V| and |E|, keeps the best graph, and derives
-//                   the threshold of the next pass.
+//                   walk list form one flat range cut into equal tiles, so
+//                   hub rows spread over many workgroups.  A neighbour still
+//                   present gets its survivor rank from the rank directory,
+//                   and a 16-bit record of it is appended to its rank bin;
+//                   a tile reserves space once per bin it touches.  The last
+//                   workgroup reduces |V| and |E|, keeps the best graph,
+//                   derives the next threshold and splits the bins into
+//                   apply work items.
+//   k_apply         the degree decrements.  Each work item counts its records
+//                   in LDS (one counter per rank of the bin) and writes the
+//                   counts as one partial row.
+//   k_reduce        subtracts every bin's partial rows from the survivors'
+//                   degrees (64 ranks x 16 item lanes per workgroup).
 //
 // The "barrier synchronization" between the two parts of Algorithm 1 is the
-// kernel boundary between k_mark_scatter and k_walk.
+// kernel boundary between k_mark_scatter and k_walk.  The degree decrements
+// of the paper's part 2 ("atomicSub" on the neighbour's degree) become
+// binned LDS histograms: device-scope atomics on gfx950 sustain only a few
+// tens of billions of operations per second, LDS atomics over a thousand.
 //
 // Exact integer arithmetic makes every result independent of launch shape
-// and atomic order.  The failure test deg * |V| * den <= 2(num+den)|E| is
-// evaluated as deg <= T_k with T_k = floor(2(num+den)|E| / (|V| den)), which
-// is the same test for integer deg.  The number of entries between two
-// vertices that fail together is not counted explicitly: every failed vertex
-// of current degree d has exactly d entries into the graph of the pass start,
-// so intra = sum(d) - cross, and |E| drops by cross + intra / 2.
-//
-// Vertices that fail with degree 0 have no neighbour left in the graph; their
-// rows are not walked.
+// and execution order.  The failure test deg * |V| * den <= 2(num+den)|E| is
+// evaluated as deg <= T_k with T_k = floor(2(num+den)|E| / (|V| den)), the
+// same test for integer deg.  Entries between two vertices that fail
+// together are not counted one by one: a failed vertex of degree d has
+// exactly d entries into the graph of the pass start, so intra = sum(d) -
+// cross, and |E| drops by cross + intra / 2.  A survivor u receives at most
+// deg(u) records in a pass, so the prefix of survivor degrees bounds every
+// bin exactly.  Rows of vertices that fail with degree 0 are not walked, and
+// nothing is walked in a pass that leaves no survivor.
 
 #include <hip/hip_runtime.h>
 
@@ -56,15 +64,22 @@ namespace dsg {
 // Pointers into one workspace allocation.
 struct Work {
     DevState* st;
-    int32_t* deg;         // n: current degree of every vertex still present
     int32_t* removed_at;  // n: pass of failure, kNever while present
-    uint32_t* live;       // ceil(n/32): bit v set while v is present
-    int32_t* list0;       // n: live lists of even passes
-    int32_t* list1;       // n: live lists of odd passes (and of pass 1's output)
+    uint2* dir;           // ceil(n/32): .x live bits, .y survivors before the word
+    int32_t* list0;       // n: live lists, even passes
+    int32_t* list1;       // n: live lists, odd passes
+    int32_t* deg0;        // n: degrees aligned with list0
+    int32_t* deg1;        // n: degrees aligned with list1
     int32_t* alist;       // n: walk list of the current pass
     int32_t* aoff;        // n+1: exclusive prefix of the walk list's row lengths
     int32_t* tile_first;  // walk tiles + 1: walk-list index owning each tile start
-    int4* tiles;          // mark tiles + 1: per-tile counts, then their prefix
+    int4* tiles;          // 2 per mark tile: counts, then their prefix
+    int32_t* bin_start;   // bins + 1: record-buffer start of every rank bin
+    int32_t* bin_cur;     // bins: append cursor of every rank bin
+    int2* bin_items;      // bins: (first apply item, item count)
+    int4* items;          // apply items: (bin, first record, end record, ranks)
+    int32_t* partial;     // items x part_stride: per-item counts
+    uint16_t* recs;       // 2m: 16-bit local ranks, grouped by bin
     PassRecord* trace;    // kTraceCap
 };
 
@@ -73,8 +88,14 @@ static_assert(sizeof(PassRecord) == sizeof(dsg_pass_trace), "trace layout");
 __device__ inline const int32_t* live_in(const Work& w, int32_t pass) {
     return pass == 1 ? nullptr : ((pass - 1) & 1 ? w.list1 : w.list0);
 }
+__device__ inline int32_t* deg_in(const Work& w, int32_t pass) {
+    return (pass - 1) & 1 ? w.deg1 : w.deg0;
+}
 __device__ inline int32_t* live_out(const Work& w, int32_t pass) {
     return (pass & 1) ? w.list1 : w.list0;
+}
+__device__ inline int32_t* deg_out(const Work& w, int32_t pass) {
+    return (pass & 1) ? w.deg1 : w.deg0;
 }
 
 // ------------------------------------------------------------------ init
@@ -82,7 +103,8 @@ __device__ inline int32_t* live_out(const Work& w, int32_t pass) {
 // racing the initialisation of the state.
 
 __global__ void k_init_state(Work w, const int32_t* __restrict__ rp, int64_t n, int64_t m,
-                             int64_t num, int64_t den, int32_t max_pass, int32_t trace_cap) {
+                             int64_t num, int64_t den, int32_t max_pass, int32_t trace_cap,
+                             int32_t part_stride, int32_t max_items) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     DevState* st = w.st;
     st->S = n;
@@ -91,10 +113,11 @@ __global__ void k_init_state(Work w, const int32_t* __restrict__ rp, int64_t n, 
     st->best_S = n;
     st->eps_num = num;
     st->eps_den = den;
-    st->nA = st->nL = st->edges = st->sumdeg = 0;
+    st->nA = st->nL = st->edges = st->sumdeg = st->sumdeg_surv = 0;
     st->cross = 0;
     st->best_count = 0;
     st->tot_walked = st->tot_cross = st->tot_live = st->tot_alist = 0;
+    st->chunk = 0;
     st->pass = 1;
     st->T = pass_threshold(m, n, num, den);
     st->best_pass = 0;
@@ -104,6 +127,10 @@ __global__ void k_init_state(Work w, const int32_t* __restrict__ rp, int64_t n, 
     st->max_pass = max_pass;
     st->trace_cap = trace_cap;
     st->n_tiles_walk = 0;
+    st->nbins = 0;
+    st->n_items = 0;
+    st->part_stride = part_stride;
+    st->max_items = max_items;
     if (rp[0] != 0 || (int64_t)rp[n] != 2 * m) {
         st->status = kStBadRowPtr;
         st->done = 1;
@@ -115,15 +142,13 @@ __global__ __launch_bounds__(kBlock) void k_init(Work w, const int32_t* __restri
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     bool bad = false;
     for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += stride) {
-        const int32_t d = rp[v + 1] - rp[v];
-        bad |= d < 0;
-        w.deg[v] = d;
+        bad |= rp[v + 1] < rp[v];
         w.removed_at[v] = kNever;
     }
     const int64_t nw = (n + 31) >> 5;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nw; i += stride) {
         const int64_t left = n - i * 32;
-        w.live[i] = left >= 32 ? 0xFFFFFFFFu : ((1u << left) - 1u);
+        w.dir[i] = make_uint2(left >= 32 ? 0xFFFFFFFFu : ((1u << left) - 1u), 0u);
     }
     if (bad) {
         // every writer stores the same values; later kernels see them
@@ -142,50 +167,58 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
     const int64_t S = st->S;
     const int32_t T = st->T;
     const int32_t* __restrict__ lin = live_in(w, pass);
+    const int32_t* __restrict__ din = deg_in(w, pass);
     const int64_t ntiles = (S + kMarkTile - 1) / kMarkTile;
     __shared__ uint32_t red[kWaves];
 
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t base = t * kMarkTile + (int64_t)threadIdx.x * kMarkItems;
-        uint32_t cA = 0, cL = 0, cE = 0, cD = 0;
+        uint32_t cA = 0, cL = 0, cE = 0, cDr = 0, cDs = 0;
         uint32_t wi = 0xFFFFFFFFu, wm = 0;
 #pragma unroll
         for (int j = 0; j < kMarkItems; ++j) {
             const int64_t idx = base + j;
             const int32_t v = idx < S ? (lin ? lin[idx] : (int32_t)idx) : -1;
             if ((uint64_t)(int64_t)v < (uint64_t)n) {
-                const int32_t d = w.deg[v];
+                const int32_t d = pass == 1 ? rp[v + 1] - rp[v] : din[idx];
                 if (d <= T) {
                     w.removed_at[v] = pass;
                     const uint32_t word = (uint32_t)v >> 5;
                     if (word != wi) {
-                        if (wm) atomicAnd(&w.live[wi], ~wm);
+                        if (wm) atomicAnd(&w.dir[wi].x, ~wm);
                         wi = word;
                         wm = 0;
                     }
                     wm |= 1u << (v & 31);
+                    cDr += (uint32_t)d;
                     if (d > 0) {
                         ++cA;
                         cE += (uint32_t)(rp[v + 1] - rp[v]);
-                        cD += (uint32_t)d;
                     }
                 } else {
                     ++cL;
+                    cDs += (uint32_t)d;
                 }
             }
         }
-        if (wm) atomicAnd(&w.live[wi], ~wm);
+        if (wm) atomicAnd(&w.dir[wi].x, ~wm);
         const uint32_t tA = block_sum(cA, red);
         const uint32_t tL = block_sum(cL, red);
         const uint32_t tE = block_sum(cE, red);
-        const uint32_t tD = block_sum(cD, red);
-        if (threadIdx.x == 0) w.tiles[t] = make_int4((int)tA, (int)tL, (int)tE, (int)tD);
+        const uint32_t tDr = block_sum(cDr, red);
+        const uint32_t tDs = block_sum(cDs, red);
+        if (threadIdx.x == 0) {
+            w.tiles[2 * t] = make_int4((int)tA, (int)tL, (int)tE, (int)tDr);
+            w.tiles[2 * t + 1] = make_int4((int)tDs, 0, 0, 0);
+        }
     }
 }
 
 // ---------------------------------------------------- prefix of tile counts
-// mode 0: the tiles of the current pass's live list (components A, L, E; D
-//         summed only).  mode 1: the extract tiles over 0..n-1 (component A).
+// mode 0: the tiles of the current pass's live list (prefix of failures with
+//         degree > 0, survivors, walk entries and survivor degrees; the
+//         failures' degree sum is only totalled).
+// mode 1: the extract tiles over 0..n-1 (component x).
 
 __global__ __launch_bounds__(kBlock) void k_scan_tiles(Work w, int32_t mode, int64_t n) {
     DevState* st = w.st;
@@ -199,39 +232,47 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(Work w, int32_t mode, int
     const int64_t per = (nt + kBlock - 1) / kBlock;
     const int64_t lo = std::min<int64_t>(nt, per * threadIdx.x);
     const int64_t hi = std::min<int64_t>(nt, lo + per);
-    int64_t a = 0, l = 0, e = 0, d = 0;
+    int64_t a = 0, l = 0, e = 0, dr = 0, ds = 0;
     for (int64_t i = lo; i < hi; ++i) {
-        const int4 c = w.tiles[i];
+        const int4 c = w.tiles[2 * i];
         a += c.x;
         l += c.y;
         e += (uint32_t)c.z;
-        d += (uint32_t)c.w;
+        dr += (uint32_t)c.w;
+        if (mode == 0) ds += (uint32_t)w.tiles[2 * i + 1].x;
     }
     __shared__ int64_t red[kWaves];
-    int64_t ta, tl, te;
+    int64_t ta, tl, te, tds;
     int64_t pa = block_excl_sum(a, red, &ta);
     int64_t pl = block_excl_sum(l, red, &tl);
     int64_t pe = block_excl_sum(e, red, &te);
-    const int64_t td = block_sum(d, red);
+    int64_t pds = block_excl_sum(ds, red, &tds);
+    const int64_t tdr = block_sum(dr, red);
     for (int64_t i = lo; i < hi; ++i) {
-        const int4 c = w.tiles[i];
-        w.tiles[i] = make_int4((int)pa, (int)pl, (int)pe, c.w);
+        const int4 c = w.tiles[2 * i];
+        const int32_t cds = mode == 0 ? w.tiles[2 * i + 1].x : 0;
+        w.tiles[2 * i] = make_int4((int)pa, (int)pl, (int)pe, c.w);
+        w.tiles[2 * i + 1] = make_int4((int)pds, 0, 0, 0);
         pa += c.x;
         pl += c.y;
         pe += (uint32_t)c.z;
+        pds += (uint32_t)cds;
     }
     if (threadIdx.x == 0) {
         if (mode == 0) {
             st->nA = ta;
             st->nL = tl;
             st->edges = te;
-            st->sumdeg = td;
+            st->sumdeg = tdr;
+            st->sumdeg_surv = tds;
             st->n_tiles_walk = (int32_t)((te + kWalkTile - 1) / kWalkTile);
+            st->nbins = (int32_t)((tl + kBinWidth - 1) >> kBinShift);
             st->tot_live += items;
             st->tot_alist += ta;
             st->cross = 0;
             st->ticket = 0;
             w.aoff[ta] = (int32_t)te;
+            w.bin_start[st->nbins] = (int32_t)tds;
         } else {
             st->best_count = ta;
         }
@@ -241,14 +282,17 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(Work w, int32_t mode, int
 // ---------------------------------------------------------- mark: scatter
 
 __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* __restrict__ rp,
-                                                         int64_t n, int64_t walk_cap) {
+                                                         int64_t n, int64_t walk_cap,
+                                                         int64_t bin_cap) {
     const DevState* st = w.st;
     if (st->done) return;
     const int32_t pass = st->pass;
     const int64_t S = st->S;
     const int32_t T = st->T;
     const int32_t* __restrict__ lin = live_in(w, pass);
+    const int32_t* __restrict__ din = deg_in(w, pass);
     int32_t* __restrict__ lout = live_out(w, pass);
+    int32_t* __restrict__ dout = deg_out(w, pass);
     const int64_t ntiles = (S + kMarkTile - 1) / kMarkTile;
     __shared__ uint32_t red[kWaves];
 
@@ -257,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
         int32_t vv[kMarkItems];
         int32_t dd[kMarkItems];
         int32_t ll[kMarkItems];
-        uint32_t cA = 0, cL = 0, cE = 0;
+        uint32_t cA = 0, cL = 0, cE = 0, cDs = 0;
 #pragma unroll
         for (int j = 0; j < kMarkItems; ++j) {
             const int64_t idx = base + j;
@@ -266,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
             ll[j] = 0;
             const int32_t v = idx < S ? (lin ? lin[idx] : (int32_t)idx) : -1;
             if ((uint64_t)(int64_t)v < (uint64_t)n) {
-                const int32_t d = w.deg[v];
+                const int32_t d = pass == 1 ? rp[v + 1] - rp[v] : din[idx];
                 vv[j] = v;
                 dd[j] = d;
                 if (d <= T) {
@@ -277,20 +321,30 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
                     }
                 } else {
                     ++cL;
+                    cDs += (uint32_t)d;
                 }
             }
         }
-        uint32_t tot_packed, tot_e;
+        // the element before this thread's first one decides word leadership
+        int32_t prev = -1;
+        if (base > 0 && base - 1 < S) prev = lin ? lin[base - 1] : (int32_t)(base - 1);
+
+        uint32_t tot_packed, tot_e, tot_ds;
         const uint32_t ex_packed = block_excl_sum(cA | (cL << 16), red, &tot_packed);
         const uint32_t ex_e = block_excl_sum(cE, red, &tot_e);
-        const int4 tp = w.tiles[t];
+        const uint32_t ex_ds = block_excl_sum(cDs, red, &tot_ds);
+        const int4 tp = w.tiles[2 * t];
+        const int4 tq = w.tiles[2 * t + 1];
         int64_t pA = (int64_t)tp.x + (ex_packed & 0xFFFFu);
         int64_t pL = (int64_t)tp.y + (ex_packed >> 16);
         int64_t pE = (int64_t)(uint32_t)tp.z + ex_e;
+        int64_t pD = (int64_t)(uint32_t)tq.x + ex_ds;
 #pragma unroll
         for (int j = 0; j < kMarkItems; ++j) {
             const int32_t v = vv[j];
             if (v < 0) continue;
+            if (prev < 0 || (prev >> 5) != (v >> 5)) w.dir[v >> 5].y = (uint32_t)pL;
+            prev = v;
             if (dd[j] <= T) {
                 if (dd[j] > 0 && pA < n) {
                     w.alist[pA] = v;
@@ -304,66 +358,121 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
                     pE += len;
                 }
             } else if (pL < n) {
-                lout[pL++] = v;
+                lout[pL] = v;
+                dout[pL] = dd[j];
+                if ((pL & (kBinWidth - 1)) == 0 && (pL >> kBinShift) < bin_cap) {
+                    w.bin_start[pL >> kBinShift] = (int32_t)pD;
+                    w.bin_cur[pL >> kBinShift] = (int32_t)pD;
+                }
+                ++pL;
+                pD += dd[j];
             }
         }
     }
 }
 
 // --------------------------------------------------------- pass completion
+// Run by every thread of the last walk workgroup.
 
-__device__ void finish_pass(const Work& w) {
+__device__ void finish_pass(const Work& w, int32_t* s_flag, int32_t* red) {
     DevState* st = w.st;
-    if (st->status != kStOk) {
-        st->done = 1;
+    if (threadIdx.x == 0) {
+        int32_t keep = 1;
+        const int64_t cross = (int64_t)atomic_load_u64(&st->cross);
+        const int64_t S_in = st->S, E_in = st->E;
+        const int64_t S_out = st->nL;
+        const int64_t intra = st->sumdeg - cross;
+        const int32_t pass = st->pass;
+        const int64_t E_out = E_in - cross - intra / 2;
+        if (st->status != kStOk || intra < 0 || (intra & 1) || E_out < 0 ||
+            (S_out == 0 && E_out != 0)) {
+            if (st->status == kStOk) st->status = kStInvariant;
+            st->done = 1;
+            keep = 0;
+        } else {
+            if (pass <= st->trace_cap) {
+                PassRecord r;
+                r.s_in = S_in;
+                r.e_in = E_in;
+                r.thresh = st->T;
+                r.removed = S_in - S_out;
+                r.cross = cross;
+                r.intra = intra;
+                r.walked = S_out > 0 ? st->edges : 0;
+                r.s_out = S_out;
+                r.e_out = E_out;
+                w.trace[pass - 1] = r;
+            }
+            st->tot_walked += S_out > 0 ? st->edges : 0;
+            st->tot_cross += cross;
+            if (S_out > 0 && E_out * st->best_S > st->best_E * S_out) {
+                st->best_E = E_out;
+                st->best_S = S_out;
+                st->best_pass = pass;
+            }
+            st->S = S_out;
+            st->E = E_out;
+            __hip_atomic_store(&st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (S_out == 0) {
+                st->done = 1;
+                keep = 0;
+            } else if (pass + 1 > st->max_pass) {
+                st->status = kStWatchdog;
+                st->done = 1;
+                keep = 0;
+            } else {
+                st->T = pass_threshold(E_out, S_out, st->eps_num, st->eps_den);
+                st->pass = pass + 1;
+                st->chunk = std::max<int64_t>(kChunkMin, (cross + kTargetItems - 1) / kTargetItems);
+            }
+        }
+        *s_flag = keep;
+    }
+    __syncthreads();
+    if (!*s_flag) {
+        if (threadIdx.x == 0) st->n_items = 0;
         return;
     }
-    const int64_t cross = (int64_t)atomic_load_u64(&st->cross);
-    const int64_t S_in = st->S, E_in = st->E;
-    const int64_t S_out = st->nL;
-    const int64_t intra = st->sumdeg - cross;
-    const int32_t pass = st->pass;
-    const int64_t E_out = E_in - cross - intra / 2;
-    if (intra < 0 || (intra & 1) || E_out < 0 || (S_out == 0 && E_out != 0)) {
-        st->status = kStInvariant;
-        st->done = 1;
-        return;
+    // split every survivor-rank bin into apply work items of <= chunk records
+    const int32_t nb = st->nbins;
+    const int64_t ch = st->chunk;
+    const int64_t nL = st->nL;
+    const int32_t per = (nb + kBlock - 1) / kBlock;
+    const int32_t lo = std::min<int32_t>(nb, per * (int32_t)threadIdx.x);
+    const int32_t hi = std::min<int32_t>(nb, lo + per);
+    int32_t cnt = 0;
+    for (int32_t b = lo; b < hi; ++b) {
+        const int64_t fill = (int64_t)__hip_atomic_load(&w.bin_cur[b], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT) -
+                             w.bin_start[b];
+        cnt += (int32_t)((fill + ch - 1) / ch);
     }
-    if (pass <= st->trace_cap) {
-        PassRecord r;
-        r.s_in = S_in;
-        r.e_in = E_in;
-        r.thresh = st->T;
-        r.removed = S_in - S_out;
-        r.cross = cross;
-        r.intra = intra;
-        r.walked = st->edges;
-        r.s_out = S_out;
-        r.e_out = E_out;
-        w.trace[pass - 1] = r;
+    int32_t total;
+    int32_t first = block_excl_sum(cnt, red, &total);
+    const int32_t cap = st->max_items;
+    for (int32_t b = lo; b < hi; ++b) {
+        const int64_t s0 = w.bin_start[b];
+        const int64_t fill = (int64_t)__hip_atomic_load(&w.bin_cur[b], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT) - s0;
+        const int32_t k = (int32_t)((fill + ch - 1) / ch);
+        const int32_t ranks = (int32_t)std::min<int64_t>(kBinWidth, nL - ((int64_t)b << kBinShift));
+        w.bin_items[b] = make_int2(first, first + k <= cap ? k : 0);
+        for (int32_t j = 0; j < k && first + j < cap; ++j) {
+            const int64_t a = s0 + (int64_t)j * ch;
+            const int64_t z = std::min<int64_t>(s0 + fill, a + ch);
+            w.items[first + j] = make_int4(b, (int)a, (int)z, ranks);
+        }
+        first += k;
     }
-    st->tot_walked += st->edges;
-    st->tot_cross += cross;
-    if (S_out > 0 && E_out * st->best_S > st->best_E * S_out) {
-        st->best_E = E_out;
-        st->best_S = S_out;
-        st->best_pass = pass;
+    if (threadIdx.x == 0) {
+        if (total > cap) {  // cannot happen: the chunk size bounds the item count
+            st->status = kStInvariant;
+            st->done = 1;
+            st->n_items = 0;
+        } else {
+            st->n_items = total;
+        }
     }
-    st->S = S_out;
-    st->E = E_out;
-    __hip_atomic_store(&st->cross, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (S_out == 0) {
-        st->done = 1;
-        return;
-    }
-    if (pass + 1 > st->max_pass) {
-        st->status = kStWatchdog;
-        st->done = 1;
-        return;
-    }
-    st->T = pass_threshold(E_out, S_out, st->eps_num, st->eps_den);
-    st->pass = pass + 1;
 }
 
 // ------------------------------------------------------------------ walk
@@ -375,14 +484,22 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
     if (st->done) return;
     const int64_t nA = st->nA;
     const int64_t total = st->edges;
-    const int64_t ntiles = st->n_tiles_walk;
-    int32_t* __restrict__ deg = w.deg;
-    const uint32_t* __restrict__ live = w.live;
+    // no survivor: no decrement is possible and the rows need no walk
+    const int64_t ntiles = st->nL > 0 ? st->n_tiles_walk : 0;
+    const int32_t nb = st->nbins;
+    const bool lds_bins = nb <= kNbLds;
+    const uint2* __restrict__ dir = w.dir;
+    int32_t* __restrict__ bin_cur = w.bin_cur;
+    uint16_t* __restrict__ recs = w.recs;
 
     __shared__ __align__(16) int32_t own[kWalkTile];
     __shared__ int32_t bas[kWalkTile + 1];
+    __shared__ int32_t tcount[kNbLds];
+    __shared__ int32_t gbase[kNbLds];
     __shared__ int32_t red[kWaves];
     __shared__ unsigned long long redc[kWaves];
+    __shared__ int32_t s_last;
+    __shared__ int32_t s_keep;
 
     uint32_t cross = 0;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -392,12 +509,14 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
         const int64_t ihi = (t + 1 < ntiles) ? (int64_t)w.tile_first[t + 1] : nA - 1;
         if (i0 < 0 || ihi >= nA || ihi < i0 || ihi - i0 + 1 > kWalkTile + 1) {
             // cannot happen for a consistent walk list; never index with it
-            if (threadIdx.x == 0) w.st->status = kStInvariant;
+            if (threadIdx.x == 0) st->status = kStInvariant;
             continue;
         }
         const int32_t c = (int32_t)(ihi - i0 + 1);
 
         for (int p = threadIdx.x; p < kWalkTile; p += kBlock) own[p] = 0;
+        if (lds_bins)
+            for (int b = threadIdx.x; b < nb; b += kBlock) tcount[b] = 0;
         __syncthreads();
         for (int i = threadIdx.x; i < c; i += kBlock) {
             const int64_t a = i0 + i;
@@ -431,19 +550,72 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
             if (p < len) {
                 const int64_t pos = (int64_t)bas[own[p]] + e0 + p;
                 if ((uint64_t)pos < (uint64_t)nnz) {
-                    const int32_t x = ci[pos];
+                    const int32_t x = __builtin_nontemporal_load(&ci[pos]);
                     u[j] = (int64_t)(uint32_t)x < n ? x : -1;  // ids outside 0..n-1 are ignored
                 }
             }
         }
-        uint32_t word[kWalkItems];
-#pragma unroll
-        for (int j = 0; j < kWalkItems; ++j) word[j] = u[j] >= 0 ? live[u[j] >> 5] : 0u;
+        // survivor rank of every neighbour still present, else -1
+        int32_t rk[kWalkItems];
 #pragma unroll
         for (int j = 0; j < kWalkItems; ++j) {
-            if (u[j] >= 0 && ((word[j] >> (u[j] & 31)) & 1u)) {
-                __hip_atomic_fetch_add(&deg[u[j]], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ++cross;
+            rk[j] = -1;
+            if (u[j] >= 0) {
+                const uint2 d = dir[u[j] >> 5];
+                const uint32_t bit = 1u << (u[j] & 31);
+                if (d.x & bit) rk[j] = (int32_t)(d.y + __popc(d.x & (bit - 1u)));
+            }
+        }
+        int32_t slot[kWalkItems];
+        if (lds_bins) {
+            if (nb <= kWaveAggBins) {
+                // few bins: one LDS atomic per (wave, bin); lanes of a bin take
+                // consecutive slots, so their records are stored contiguously
+                const int lane = lane_id();
+                const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+                for (int j = 0; j < kWalkItems; ++j) {
+                    const int32_t my_bin = rk[j] >= 0 ? rk[j] >> kBinShift : -1;
+                    unsigned long long active = __ballot(my_bin >= 0);
+                    slot[j] = 0;
+                    while (active) {
+                        const int leader = __ffsll((long long)active) - 1;
+                        const int32_t b = __shfl(my_bin, leader, 64);
+                        const unsigned long long same = __ballot(my_bin == b);
+                        int32_t at = 0;
+                        if (lane == leader) at = atomicAdd(&tcount[b], (int32_t)__popcll(same));
+                        at = __shfl(at, leader, 64);
+                        if (my_bin == b) slot[j] = at + (int32_t)__popcll(same & below);
+                        active &= ~same;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < kWalkItems; ++j)
+                    slot[j] = rk[j] >= 0 ? atomicAdd(&tcount[rk[j] >> kBinShift], 1) : 0;
+            }
+            __syncthreads();
+            for (int b = threadIdx.x; b < nb; b += kBlock) {
+                const int32_t k = tcount[b];
+                if (k) gbase[b] = atomicAdd(&bin_cur[b], k);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kWalkItems; ++j) {
+                if (rk[j] >= 0) {
+                    recs[(int64_t)gbase[rk[j] >> kBinShift] + slot[j]] =
+                        (uint16_t)(rk[j] & (kBinWidth - 1));
+                    ++cross;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kWalkItems; ++j) {
+                if (rk[j] >= 0) {
+                    const int32_t at = atomicAdd(&bin_cur[rk[j] >> kBinShift], 1);
+                    recs[at] = (uint16_t)(rk[j] & (kBinWidth - 1));
+                    ++cross;
+                }
             }
         }
         __syncthreads();
@@ -453,10 +625,82 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
         if (bc) atomicAdd(&st->cross, bc);
         __threadfence();
         const uint32_t tk = atomicAdd(&st->ticket, 1u);
-        if (tk == gridDim.x - 1) {
-            __threadfence();
-            finish_pass(w);
+        s_last = tk == gridDim.x - 1;
+        if (s_last) __threadfence();
+    }
+    __syncthreads();
+    if (s_last) finish_pass(w, &s_keep, red);
+}
+
+// ----------------------------------------------------------------- apply
+// One work item = up to `chunk` records of one bin: count them per rank in
+// LDS and store the counts as a partial row.
+
+__global__ __launch_bounds__(kApplyBlock) void k_apply(Work w) {
+    const DevState* st = w.st;
+    const int32_t n_items = st->n_items;
+    if (n_items == 0) return;
+    const int32_t stride = st->part_stride;
+    __shared__ int32_t cnt[kBinWidth];
+    const uint16_t* __restrict__ recs = w.recs;
+    for (int32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int4 item = w.items[it];
+        const int32_t ranks = item.w;
+        for (int i = threadIdx.x; i < ranks; i += kApplyBlock) cnt[i] = 0;
+        __syncthreads();
+        int64_t e = (int64_t)item.y + threadIdx.x;
+        const int64_t z = item.z;
+        for (; e + 3 * kApplyBlock < z; e += 4 * kApplyBlock) {
+            const uint32_t r0 = recs[e], r1 = recs[e + kApplyBlock];
+            const uint32_t r2 = recs[e + 2 * kApplyBlock], r3 = recs[e + 3 * kApplyBlock];
+            atomicAdd(&cnt[r0], 1);
+            atomicAdd(&cnt[r1], 1);
+            atomicAdd(&cnt[r2], 1);
+            atomicAdd(&cnt[r3], 1);
         }
+        for (; e < z; e += kApplyBlock) atomicAdd(&cnt[recs[e]], 1);
+        __syncthreads();
+        int32_t* __restrict__ out = w.partial + (int64_t)it * stride;
+        for (int i = threadIdx.x; i < ranks; i += kApplyBlock) out[i] = cnt[i];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- reduce
+// degree[r] -= sum of the partial rows of r's bin, for every survivor rank r
+// of the pass just finished.  64 consecutive ranks share a bin.
+
+constexpr int kReduceRanks = 64;
+constexpr int kReduceLanes = kApplyBlock / kReduceRanks;
+
+__global__ __launch_bounds__(kApplyBlock) void k_reduce(Work w) {
+    const DevState* st = w.st;
+    if (st->n_items == 0) return;
+    const int64_t nL = st->nL;
+    const int32_t stride = st->part_stride;
+    int32_t* __restrict__ deg = deg_in(w, st->pass);  // the pass counter has advanced
+    const int64_t ntasks = (nL + kReduceRanks - 1) / kReduceRanks;
+    const int rl = threadIdx.x % kReduceRanks;
+    const int lane = threadIdx.x / kReduceRanks;
+    __shared__ int32_t part[kReduceLanes][kReduceRanks];
+    for (int64_t task = blockIdx.x; task < ntasks; task += gridDim.x) {
+        const int64_t r = task * kReduceRanks + rl;
+        int32_t sum = 0;
+        if (r < nL) {
+            const int2 bi = w.bin_items[r >> kBinShift];
+            const int32_t* __restrict__ p =
+                w.partial + (int64_t)bi.x * stride + (r & (kBinWidth - 1));
+            for (int32_t i = lane; i < bi.y; i += kReduceLanes) sum += p[(int64_t)i * stride];
+        }
+        part[lane][rl] = sum;
+        __syncthreads();
+        if (lane == 0 && r < nL) {
+            int32_t tot = 0;
+#pragma unroll
+            for (int l = 0; l < kReduceLanes; ++l) tot += part[l][rl];
+            if (tot) deg[r] -= tot;
+        }
+        __syncthreads();
     }
 }
 
@@ -476,7 +720,7 @@ __global__ __launch_bounds__(kBlock) void k_extract_count(Work w, int64_t n) {
         for (int j = 0; j < kMarkItems; ++j)
             if (base + j < n && w.removed_at[base + j] > bp) ++c;
         const uint32_t tc = block_sum(c, red);
-        if (threadIdx.x == 0) w.tiles[t] = make_int4((int)tc, 0, 0, 0);
+        if (threadIdx.x == 0) w.tiles[2 * t] = make_int4((int)tc, 0, 0, 0);
     }
 }
 
@@ -498,7 +742,7 @@ __global__ __launch_bounds__(kBlock) void k_extract_scatter(Work w, int64_t n,
             }
         uint32_t tot;
         const uint32_t ex = block_excl_sum(c, red, &tot);
-        int64_t pos = (int64_t)w.tiles[t].x + ex;
+        int64_t pos = (int64_t)w.tiles[2 * t].x + ex;
 #pragma unroll
         for (int j = 0; j < kMarkItems; ++j)
             if ((keep >> j & 1u) && pos < n) best[pos++] = (int32_t)(base + j);
@@ -512,6 +756,7 @@ namespace {
 struct DevInfo {
     int cus = 0;
     int walk_blocks_per_cu = 0;
+    int apply_blocks_per_cu = 0;
     bool ready = false;
 };
 
@@ -532,8 +777,12 @@ hipError_t device_info(DevInfo* out) {
         int per = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_walk, kBlock, 0);
         if (e != hipSuccess) return e;
+        int per_apply = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_apply, k_apply, kApplyBlock, 0);
+        if (e != hipSuccess) return e;
         di.cus = cus;
         di.walk_blocks_per_cu = std::max(per, 1);
+        di.apply_blocks_per_cu = std::max(per_apply, 1);
         di.ready = true;
     }
     *out = di;
@@ -542,12 +791,23 @@ hipError_t device_info(DevInfo* out) {
 
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-struct Layout {
-    size_t st, deg, rem, live, l0, l1, alist, aoff, tfirst, tiles, trace, total;
-};
-
 inline int64_t mark_tiles(int64_t n) { return (n + kMarkTile - 1) / kMarkTile + 1; }
 inline int64_t walk_tiles(int64_t m) { return (2 * m + kWalkTile - 1) / kWalkTile + 1; }
+inline int64_t max_bins(int64_t n) { return (n + kBinWidth - 1) / kBinWidth + 1; }
+inline int64_t part_stride(int64_t n) {
+    return std::min<int64_t>(kBinWidth, std::max<int64_t>(n, 1));
+}
+// Work items per pass: every bin with records has at most one item shorter
+// than the chunk, and the chunk is at least kChunkMin and at least
+// records / kTargetItems, with records <= 2m.
+inline int64_t max_items(int64_t n, int64_t m) {
+    return max_bins(n) + std::min<int64_t>(kTargetItems, (2 * m + kChunkMin - 1) / kChunkMin) + 1;
+}
+
+struct Layout {
+    size_t st, rem, dir, l0, l1, d0, d1, alist, aoff, tfirst, tiles, bstart, bcur, bitems, items,
+        partial, recs, trace, total;
+};
 
 Layout layout(int64_t n, int64_t m) {
     Layout L;
@@ -557,16 +817,25 @@ Layout layout(int64_t n, int64_t m) {
         o = align_up(o + bytes);
         return at;
     };
+    const int64_t nb = max_bins(n);
+    const int64_t ni = max_items(n, m);
     L.st = take(sizeof(DevState));
-    L.deg = take(4 * (size_t)n);
     L.rem = take(4 * (size_t)n);
-    L.live = take(4 * (size_t)((n + 31) / 32));
+    L.dir = take(8 * (size_t)((n + 31) / 32));
     L.l0 = take(4 * (size_t)n);
     L.l1 = take(4 * (size_t)n);
+    L.d0 = take(4 * (size_t)n);
+    L.d1 = take(4 * (size_t)n);
     L.alist = take(4 * (size_t)n);
     L.aoff = take(4 * (size_t)(n + 1));
     L.tfirst = take(4 * (size_t)walk_tiles(m));
-    L.tiles = take(sizeof(int4) * (size_t)mark_tiles(n));
+    L.tiles = take(2 * sizeof(int4) * (size_t)mark_tiles(n));
+    L.bstart = take(4 * (size_t)nb);
+    L.bcur = take(4 * (size_t)nb);
+    L.bitems = take(8 * (size_t)nb);
+    L.items = take(sizeof(int4) * (size_t)ni);
+    L.partial = take(4 * (size_t)ni * (size_t)part_stride(n));
+    L.recs = take(2 * (size_t)(2 * m));
     L.trace = take(sizeof(PassRecord) * (size_t)kTraceCap);
     L.total = o;
     return L;
@@ -600,9 +869,11 @@ int32_t map_hip(hipError_t e) {
 
 thread_local DevState* t_host_state = nullptr;
 
+enum { kKindInit = 0, kKindMark = 1, kKindWalk = 2, kKindApply = 3, kKindExtract = 4 };
+
 struct EventLog {
     std::vector<hipEvent_t> ev;
-    std::vector<int> kind;  // per launch: 0 init, 1 mark, 2 walk, 3 extract
+    std::vector<int> kind;
     bool on = false;
     hipStream_t s = nullptr;
     hipError_t begin(int k) {
@@ -693,7 +964,9 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
     Work w;
     int32_t max_pass, batch;
     int64_t launched = 0;
-    unsigned mark_grid, walk_grid, init_grid;
+    unsigned mark_grid, walk_grid, init_grid, apply_grid, reduce_grid;
+    const int64_t nbins_cap = max_bins(n);
+    const int64_t items_cap = max_items(n, m);
 
     DSG_HIP(device_info(&di));
     if (!t_host_state) {
@@ -706,15 +979,22 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
         owned = true;
     }
     w.st = (DevState*)(base + L.st);
-    w.deg = (int32_t*)(base + L.deg);
     w.removed_at = removed_at ? removed_at : (int32_t*)(base + L.rem);
-    w.live = (uint32_t*)(base + L.live);
+    w.dir = (uint2*)(base + L.dir);
     w.list0 = (int32_t*)(base + L.l0);
     w.list1 = (int32_t*)(base + L.l1);
+    w.deg0 = (int32_t*)(base + L.d0);
+    w.deg1 = (int32_t*)(base + L.d1);
     w.alist = (int32_t*)(base + L.alist);
     w.aoff = (int32_t*)(base + L.aoff);
     w.tile_first = (int32_t*)(base + L.tfirst);
     w.tiles = (int4*)(base + L.tiles);
+    w.bin_start = (int32_t*)(base + L.bstart);
+    w.bin_cur = (int32_t*)(base + L.bcur);
+    w.bin_items = (int2*)(base + L.bitems);
+    w.items = (int4*)(base + L.items);
+    w.partial = (int32_t*)(base + L.partial);
+    w.recs = (uint16_t*)(base + L.recs);
     w.trace = (PassRecord*)(base + L.trace);
 
     max_pass = pass_bound(n, eps_num, eps_den);
@@ -728,32 +1008,43 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
         walk_grid = (unsigned)std::max<int64_t>(1, std::min(wg, wt));
         init_grid = (unsigned)std::max<int64_t>(
             1, std::min<int64_t>((int64_t)di.cus * 8, (n + kBlock - 1) / kBlock));
+        apply_grid = (unsigned)std::max<int64_t>(
+            1, std::min<int64_t>((int64_t)di.cus * di.apply_blocks_per_cu, items_cap));
+        reduce_grid = (unsigned)std::max<int64_t>(
+            1, std::min<int64_t>((int64_t)di.cus * 2, (n + 63) / 64));
         batch = launch && launch->pass_batch ? launch->pass_batch : std::min(max_pass, 8);
     }
 
-    DSG_HIP(log.begin(0));
+    DSG_HIP(log.begin(kKindInit));
     k_init_state<<<1, 64, 0, s>>>(w, g->row_ptr, n, m, eps_num, eps_den, max_pass,
-                                  std::min(trace_cap, kTraceCap));
+                                  std::min(trace_cap, kTraceCap), (int32_t)part_stride(n),
+                                  (int32_t)items_cap);
     k_init<<<init_grid, kBlock, 0, s>>>(w, g->row_ptr, n);
     DSG_HIP(hipGetLastError());
     DSG_HIP(log.end());
 
     for (;;) {
         for (int32_t b = 0; b < batch; ++b) {
-            DSG_HIP(log.begin(1));
+            DSG_HIP(log.begin(kKindMark));
             k_mark_count<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, n);
             k_scan_tiles<<<1, kBlock, 0, s>>>(w, 0, n);
-            k_mark_scatter<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, n, walk_tiles(m));
+            k_mark_scatter<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, n, walk_tiles(m),
+                                                        nbins_cap);
             DSG_HIP(hipGetLastError());
             DSG_HIP(log.end());
-            DSG_HIP(log.begin(2));
+            DSG_HIP(log.begin(kKindWalk));
             k_walk<<<walk_grid, kBlock, 0, s>>>(w, g->row_ptr, g->col_idx, n, 2 * m);
+            DSG_HIP(hipGetLastError());
+            DSG_HIP(log.end());
+            DSG_HIP(log.begin(kKindApply));
+            k_apply<<<apply_grid, kApplyBlock, 0, s>>>(w);
+            k_reduce<<<reduce_grid, kApplyBlock, 0, s>>>(w);
             DSG_HIP(hipGetLastError());
             DSG_HIP(log.end());
             ++launched;
         }
         if (best_ids) {
-            DSG_HIP(log.begin(3));
+            DSG_HIP(log.begin(kKindExtract));
             k_extract_count<<<mark_grid, kBlock, 0, s>>>(w, n);
             k_scan_tiles<<<1, kBlock, 0, s>>>(w, 1, n);
             k_extract_scatter<<<mark_grid, kBlock, 0, s>>>(w, n, best_ids);
@@ -803,9 +1094,10 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
                 float ms = 0.f;
                 DSG_HIP(hipEventElapsedTime(&ms, log.ev[i], log.ev[i + 1]));
                 switch (log.kind[i / 2]) {
-                    case 0: prof->ms_init += ms; break;
-                    case 1: prof->ms_mark += ms; prof->launches_mark++; break;
-                    case 2: prof->ms_walk += ms; prof->launches_walk++; break;
+                    case kKindInit: prof->ms_init += ms; break;
+                    case kKindMark: prof->ms_mark += ms; prof->launches_mark++; break;
+                    case kKindWalk: prof->ms_walk += ms; prof->launches_walk++; break;
+                    case kKindApply: prof->ms_apply += ms; prof->launches_apply++; break;
                     default: prof->ms_extract += ms; break;
                 }
             }

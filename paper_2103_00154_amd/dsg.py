@@ -51,9 +51,10 @@ class Launch(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("ms_init", ctypes.c_double), ("ms_mark", ctypes.c_double),
-                ("ms_walk", ctypes.c_double), ("ms_extract", ctypes.c_double),
-                ("ms_total", ctypes.c_double), ("launches_walk", _I32),
-                ("launches_mark", _I32), ("walked", _I64), ("cross", _I64),
+                ("ms_walk", ctypes.c_double), ("ms_apply", ctypes.c_double),
+                ("ms_extract", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("launches_walk", _I32), ("launches_mark", _I32), ("launches_apply", _I32),
+                ("reserved", _I32), ("walked", _I64), ("cross", _I64),
                 ("live_scanned", _I64), ("walk_list", _I64)]
 
 
