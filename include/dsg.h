@@ -90,8 +90,13 @@ typedef struct {
     int32_t mark_grid;  /* workgroups of the mark / extract kernels */
     int32_t walk_grid;  /* workgroups of the neighbour-walk kernel  */
     int32_t pass_batch; /* passes enqueued before the host checks for completion */
-    int32_t reserved;
+    int32_t flags;      /* DSG_LAUNCH_* bits */
 } dsg_launch;
+
+/* Keep degree-update records in per-bin regions (one device atomic per
+ * record) instead of per-tile regions.  The library does this by itself when
+ * a pass leaves more than 1024 * 32768 survivors; the flag forces it. */
+#define DSG_LAUNCH_BIN_REGIONS 1
 
 /* Optional per-kernel timing, measured with HIP events on the call's stream
  * around every launch of the call (host struct, filled on return).  Launches
@@ -120,8 +125,9 @@ int32_t dsg_version(void);
 const char* dsg_strerror(int32_t status);
 
 /* Bytes of device workspace dsg_peel needs for a graph with n vertices and
- * m undirected edges; 0 for invalid sizes.  About 28 n + 4 m bytes plus up
- * to min(n, 32768) * 4 bytes per degree-update work item (at most
+ * m undirected edges; 0 for invalid sizes.  About 28 n + 4 m bytes, plus
+ * 2 * ceil(2m / 2048) * (min(n / 32768, 1024) + 2) bytes of per-tile bin
+ * offsets and min(n, 32768) * 4 bytes per degree-update work item (at most
  * n / 32768 + 514 items). */
 size_t dsg_workspace_bytes(int64_t n, int64_t m);
 

@@ -72,7 +72,10 @@ struct alignas(256) DevState {
     int32_t n_items;    // apply work items of the current pass
     int32_t part_stride;  // ints per partial-count row (min(kBinWidth, n))
     int32_t max_items;  // capacity of the work-item table
-    int32_t pad[3];
+    int32_t walk_mode;  // 0: records in per-tile regions, 1: records in bin regions
+    int32_t toff_stride;  // entries per tile in the tile-offset table (bins + 1)
+    int32_t force_bins;   // 1: always use bin regions (launch flag)
+    int32_t apply_lanes;  // lanes that share one tile's run in k_apply (4..64)
 };
 
 struct PassRecord {

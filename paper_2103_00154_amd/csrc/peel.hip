@@ -70,7 +70,7 @@ struct Work {
     int32_t* list1;       // n: live lists, odd passes
     int32_t* deg0;        // n: degrees aligned with list0
     int32_t* deg1;        // n: degrees aligned with list1
-    int32_t* alist;       // n: walk list of the current pass
+    int32_t* arow;        // n: walk list of the current pass (CSR row start of each vertex)
     int32_t* aoff;        // n+1: exclusive prefix of the walk list's row lengths
     int32_t* tile_first;  // walk tiles + 1: walk-list index owning each tile start
     int4* tiles;          // 2 per mark tile: counts, then their prefix
@@ -79,7 +79,8 @@ struct Work {
     int2* bin_items;      // bins: (first apply item, item count)
     int4* items;          // apply items: (bin, first record, end record, ranks)
     int32_t* partial;     // items x part_stride: per-item counts
-    uint16_t* recs;       // 2m: 16-bit local ranks, grouped by bin
+    uint16_t* recs;       // walk tiles x kWalkTile: 16-bit local ranks
+    uint16_t* toff;       // walk tiles x (bins + 1): bin offsets inside each tile
     PassRecord* trace;    // kTraceCap
 };
 
@@ -104,7 +105,7 @@ __device__ inline int32_t* deg_out(const Work& w, int32_t pass) {
 
 __global__ void k_init_state(Work w, const int32_t* __restrict__ rp, int64_t n, int64_t m,
                              int64_t num, int64_t den, int32_t max_pass, int32_t trace_cap,
-                             int32_t part_stride, int32_t max_items) {
+                             int32_t part_stride, int32_t max_items, int32_t force_bins) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     DevState* st = w.st;
     st->S = n;
@@ -131,6 +132,10 @@ __global__ void k_init_state(Work w, const int32_t* __restrict__ rp, int64_t n, 
     st->n_items = 0;
     st->part_stride = part_stride;
     st->max_items = max_items;
+    st->walk_mode = 0;
+    st->toff_stride = 1;
+    st->force_bins = force_bins;
+    st->apply_lanes = 64;
     if (rp[0] != 0 || (int64_t)rp[n] != 2 * m) {
         st->status = kStBadRowPtr;
         st->done = 1;
@@ -267,6 +272,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(Work w, int32_t mode, int
             st->sumdeg_surv = tds;
             st->n_tiles_walk = (int32_t)((te + kWalkTile - 1) / kWalkTile);
             st->nbins = (int32_t)((tl + kBinWidth - 1) >> kBinShift);
+            st->walk_mode = (st->nbins <= kNbLds && !st->force_bins) ? 0 : 1;
+            st->toff_stride = st->nbins + 1;
             st->tot_live += items;
             st->tot_alist += ta;
             st->cross = 0;
@@ -347,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
             prev = v;
             if (dd[j] <= T) {
                 if (dd[j] > 0 && pA < n) {
-                    w.alist[pA] = v;
+                    w.arow[pA] = rp[v];
                     w.aoff[pA] = (int32_t)pE;
                     const int64_t len = ll[j];
                     // walk tiles whose first entry lies in [pE, pE + len)
@@ -433,10 +440,45 @@ __device__ void finish_pass(const Work& w, int32_t* s_flag, int32_t* red) {
         if (threadIdx.x == 0) st->n_items = 0;
         return;
     }
-    // split every survivor-rank bin into apply work items of <= chunk records
     const int32_t nb = st->nbins;
-    const int64_t ch = st->chunk;
     const int64_t nL = st->nL;
+    if (st->walk_mode == 0) {
+        // records sit in per-tile regions: an item is one bin over a range of
+        // tiles; a bin's items are consecutive
+        const int32_t cap_a = st->max_items;
+        const int64_t ntiles = st->n_tiles_walk;
+        const int64_t ipb = std::max<int64_t>(1, std::min<int64_t>(ntiles, kTargetItems / nb));
+        const int64_t tpi = (ntiles + ipb - 1) / ipb;
+        const int64_t total_a = (int64_t)nb * ipb;
+        for (int64_t i = threadIdx.x; i < total_a && i < cap_a; i += kBlock) {
+            const int32_t b = (int32_t)(i / ipb);
+            const int64_t t0 = std::min<int64_t>(ntiles, (i % ipb) * tpi);
+            const int64_t t1 = std::min<int64_t>(ntiles, t0 + tpi);
+            const int32_t ranks =
+                (int32_t)std::min<int64_t>(kBinWidth, nL - ((int64_t)b << kBinShift));
+            w.items[i] = make_int4(b, (int)t0, (int)t1, ranks);
+        }
+        for (int32_t b = threadIdx.x; b < nb; b += kBlock)
+            w.bin_items[b] = make_int2((int)(b * ipb), total_a <= cap_a ? (int)ipb : 0);
+        if (threadIdx.x == 0) {
+            // lanes per (tile, bin) run in k_apply: about half the mean run
+            const int64_t runs = std::max<int64_t>(1, ntiles * nb);
+            const int64_t mean = (int64_t)atomic_load_u64(&st->cross) / runs;
+            int32_t lanes = 4;
+            while (lanes < 64 && 2 * lanes < mean) lanes *= 2;
+            st->apply_lanes = lanes;
+            if (total_a > cap_a) {  // cannot happen: nb * ipb <= max(nb, kTargetItems)
+                st->status = kStInvariant;
+                st->done = 1;
+                st->n_items = 0;
+            } else {
+                st->n_items = (int32_t)total_a;
+            }
+        }
+        return;
+    }
+    // records sit in bin regions: split every bin into items of <= chunk records
+    const int64_t ch = st->chunk;
     const int32_t per = (nb + kBlock - 1) / kBlock;
     const int32_t lo = std::min<int32_t>(nb, per * (int32_t)threadIdx.x);
     const int32_t hi = std::min<int32_t>(nb, lo + per);
@@ -487,15 +529,14 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
     // no survivor: no decrement is possible and the rows need no walk
     const int64_t ntiles = st->nL > 0 ? st->n_tiles_walk : 0;
     const int32_t nb = st->nbins;
-    const bool lds_bins = nb <= kNbLds;
+    const bool lds_bins = st->walk_mode == 0;
     const uint2* __restrict__ dir = w.dir;
     int32_t* __restrict__ bin_cur = w.bin_cur;
     uint16_t* __restrict__ recs = w.recs;
 
     __shared__ __align__(16) int32_t own[kWalkTile];
     __shared__ int32_t bas[kWalkTile + 1];
-    __shared__ int32_t tcount[kNbLds];
-    __shared__ int32_t gbase[kNbLds];
+    __shared__ int32_t tcount[kNbLds];  // per-tile bin counts, then their offsets
     __shared__ int32_t red[kWaves];
     __shared__ unsigned long long redc[kWaves];
     __shared__ int32_t s_last;
@@ -521,8 +562,7 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
         for (int i = threadIdx.x; i < c; i += kBlock) {
             const int64_t a = i0 + i;
             const int32_t off = w.aoff[a];
-            const int32_t v = w.alist[a];
-            bas[i] = rp[v] - off;
+            bas[i] = w.arow[a] - off;
             const int64_t o = (int64_t)off - e0;
             if (o < len) own[o > 0 ? o : 0] = i;
         }
@@ -595,16 +635,30 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
                     slot[j] = rk[j] >= 0 ? atomicAdd(&tcount[rk[j] >> kBinShift], 1) : 0;
             }
             __syncthreads();
-            for (int b = threadIdx.x; b < nb; b += kBlock) {
-                const int32_t k = tcount[b];
-                if (k) gbase[b] = atomicAdd(&bin_cur[b], k);
+            {
+                // this tile's records go to its own region, grouped by bin:
+                // exclusive prefix of the bin counts, also kept in the table
+                const int q = (nb + kBlock - 1) / kBlock;
+                const int b0 = min(nb, q * (int)threadIdx.x), b1 = min(nb, b0 + q);
+                int32_t s = 0;
+                for (int b = b0; b < b1; ++b) s += tcount[b];
+                int32_t all;
+                int32_t at = block_excl_sum(s, red, &all);
+                uint16_t* __restrict__ to = w.toff + t * (int64_t)(nb + 1);
+                for (int b = b0; b < b1; ++b) {
+                    const int32_t k = tcount[b];
+                    tcount[b] = at;
+                    to[b] = (uint16_t)at;
+                    at += k;
+                }
+                if (threadIdx.x == 0) to[nb] = (uint16_t)all;
             }
             __syncthreads();
+            uint16_t* __restrict__ tr = recs + t * (int64_t)kWalkTile;
 #pragma unroll
             for (int j = 0; j < kWalkItems; ++j) {
                 if (rk[j] >= 0) {
-                    recs[(int64_t)gbase[rk[j] >> kBinShift] + slot[j]] =
-                        (uint16_t)(rk[j] & (kBinWidth - 1));
+                    tr[tcount[rk[j] >> kBinShift] + slot[j]] = (uint16_t)(rk[j] & (kBinWidth - 1));
                     ++cross;
                 }
             }
@@ -633,32 +687,49 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
 }
 
 // ----------------------------------------------------------------- apply
-// One work item = up to `chunk` records of one bin: count them per rank in
-// LDS and store the counts as a partial row.
+// One work item = the records of one bin over a range of walk tiles (or one
+// range of a bin region): count them per rank in LDS and store the counts as
+// a partial row.
 
 __global__ __launch_bounds__(kApplyBlock) void k_apply(Work w) {
     const DevState* st = w.st;
     const int32_t n_items = st->n_items;
     if (n_items == 0) return;
     const int32_t stride = st->part_stride;
+    const int32_t mode = st->walk_mode;
+    const int64_t tstride = st->toff_stride;
     __shared__ int32_t cnt[kBinWidth];
     const uint16_t* __restrict__ recs = w.recs;
+    const int lanes = st->apply_lanes;
+    const int groups = kApplyBlock / lanes;
+    const int grp = threadIdx.x / lanes;
+    const int sub = threadIdx.x % lanes;
     for (int32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int4 item = w.items[it];
         const int32_t ranks = item.w;
         for (int i = threadIdx.x; i < ranks; i += kApplyBlock) cnt[i] = 0;
         __syncthreads();
-        int64_t e = (int64_t)item.y + threadIdx.x;
-        const int64_t z = item.z;
-        for (; e + 3 * kApplyBlock < z; e += 4 * kApplyBlock) {
-            const uint32_t r0 = recs[e], r1 = recs[e + kApplyBlock];
-            const uint32_t r2 = recs[e + 2 * kApplyBlock], r3 = recs[e + 3 * kApplyBlock];
-            atomicAdd(&cnt[r0], 1);
-            atomicAdd(&cnt[r1], 1);
-            atomicAdd(&cnt[r2], 1);
-            atomicAdd(&cnt[r3], 1);
+        if (mode == 0) {
+            // groups of `lanes` threads walk one tile's run of this bin's records
+            for (int64_t tt = (int64_t)item.y + grp; tt < item.z; tt += groups) {
+                const uint16_t* __restrict__ o = w.toff + tt * tstride + item.x;
+                const int32_t s = o[0], e = o[1];
+                const uint16_t* __restrict__ r = recs + tt * (int64_t)kWalkTile;
+                for (int32_t x = s + sub; x < e; x += lanes) atomicAdd(&cnt[r[x]], 1);
+            }
+        } else {
+            int64_t e = (int64_t)item.y + threadIdx.x;
+            const int64_t z = item.z;
+            for (; e + 3 * kApplyBlock < z; e += 4 * kApplyBlock) {
+                const uint32_t r0 = recs[e], r1 = recs[e + kApplyBlock];
+                const uint32_t r2 = recs[e + 2 * kApplyBlock], r3 = recs[e + 3 * kApplyBlock];
+                atomicAdd(&cnt[r0], 1);
+                atomicAdd(&cnt[r1], 1);
+                atomicAdd(&cnt[r2], 1);
+                atomicAdd(&cnt[r3], 1);
+            }
+            for (; e < z; e += kApplyBlock) atomicAdd(&cnt[recs[e]], 1);
         }
-        for (; e < z; e += kApplyBlock) atomicAdd(&cnt[recs[e]], 1);
         __syncthreads();
         int32_t* __restrict__ out = w.partial + (int64_t)it * stride;
         for (int i = threadIdx.x; i < ranks; i += kApplyBlock) out[i] = cnt[i];
@@ -781,7 +852,9 @@ hipError_t device_info(DevInfo* out) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_apply, k_apply, kApplyBlock, 0);
         if (e != hipSuccess) return e;
         di.cus = cus;
-        di.walk_blocks_per_cu = std::max(per, 1);
+        // more than 6 resident walk workgroups per CU measured slower (the
+        // rank-directory gathers of extra tiles evict each other from L2)
+        di.walk_blocks_per_cu = std::max(std::min(per, 6), 1);
         di.apply_blocks_per_cu = std::max(per_apply, 1);
         di.ready = true;
     }
@@ -797,16 +870,23 @@ inline int64_t max_bins(int64_t n) { return (n + kBinWidth - 1) / kBinWidth + 1;
 inline int64_t part_stride(int64_t n) {
     return std::min<int64_t>(kBinWidth, std::max<int64_t>(n, 1));
 }
-// Work items per pass: every bin with records has at most one item shorter
-// than the chunk, and the chunk is at least kChunkMin and at least
-// records / kTargetItems, with records <= 2m.
+// Work items per pass.  Per-tile records: nb * min(tiles, kTargetItems / nb)
+// items (at least nb), nb <= kNbLds.  Bin regions: every bin with records
+// has at most one item shorter than the chunk, and the chunk is at least
+// kChunkMin and at least records / kTargetItems, with records <= 2m.
 inline int64_t max_items(int64_t n, int64_t m) {
-    return max_bins(n) + std::min<int64_t>(kTargetItems, (2 * m + kChunkMin - 1) / kChunkMin) + 1;
+    const int64_t nb = max_bins(n);
+    const int64_t tile_items =
+        std::min<int64_t>(std::max<int64_t>(kTargetItems, std::min<int64_t>(nb, kNbLds)),
+                          nb * walk_tiles(m));
+    const int64_t bin_items =
+        nb + std::min<int64_t>(kTargetItems, (2 * m + kChunkMin - 1) / kChunkMin) + 1;
+    return std::max(tile_items, bin_items);
 }
 
 struct Layout {
-    size_t st, rem, dir, l0, l1, d0, d1, alist, aoff, tfirst, tiles, bstart, bcur, bitems, items,
-        partial, recs, trace, total;
+    size_t st, rem, dir, l0, l1, d0, d1, arow, aoff, tfirst, tiles, bstart, bcur, bitems, items,
+        partial, recs, toff, trace, total;
 };
 
 Layout layout(int64_t n, int64_t m) {
@@ -826,7 +906,7 @@ Layout layout(int64_t n, int64_t m) {
     L.l1 = take(4 * (size_t)n);
     L.d0 = take(4 * (size_t)n);
     L.d1 = take(4 * (size_t)n);
-    L.alist = take(4 * (size_t)n);
+    L.arow = take(4 * (size_t)n);
     L.aoff = take(4 * (size_t)(n + 1));
     L.tfirst = take(4 * (size_t)walk_tiles(m));
     L.tiles = take(2 * sizeof(int4) * (size_t)mark_tiles(n));
@@ -835,7 +915,8 @@ Layout layout(int64_t n, int64_t m) {
     L.bitems = take(8 * (size_t)nb);
     L.items = take(sizeof(int4) * (size_t)ni);
     L.partial = take(4 * (size_t)ni * (size_t)part_stride(n));
-    L.recs = take(2 * (size_t)(2 * m));
+    L.recs = take(2 * (size_t)walk_tiles(m) * kWalkTile);
+    L.toff = take(2 * (size_t)walk_tiles(m) * (size_t)(std::min<int64_t>(nb, kNbLds) + 1));
     L.trace = take(sizeof(PassRecord) * (size_t)kTraceCap);
     L.total = o;
     return L;
@@ -879,7 +960,7 @@ struct EventLog {
     hipError_t begin(int k) {
         if (!on) return hipSuccess;
         hipEvent_t a;
-        hipError_t e = hipEventCreate(&a);
+        hipError_t e = hipEventCreateWithFlags(&a, hipEventDisableSystemFence);
         if (e != hipSuccess) return e;
         ev.push_back(a);
         kind.push_back(k);
@@ -888,7 +969,7 @@ struct EventLog {
     hipError_t end() {
         if (!on) return hipSuccess;
         hipEvent_t b;
-        hipError_t e = hipEventCreate(&b);
+        hipError_t e = hipEventCreateWithFlags(&b, hipEventDisableSystemFence);
         if (e != hipSuccess) return e;
         ev.push_back(b);
         return hipEventRecord(b, s);
@@ -985,7 +1066,7 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
     w.list1 = (int32_t*)(base + L.l1);
     w.deg0 = (int32_t*)(base + L.d0);
     w.deg1 = (int32_t*)(base + L.d1);
-    w.alist = (int32_t*)(base + L.alist);
+    w.arow = (int32_t*)(base + L.arow);
     w.aoff = (int32_t*)(base + L.aoff);
     w.tile_first = (int32_t*)(base + L.tfirst);
     w.tiles = (int4*)(base + L.tiles);
@@ -995,6 +1076,7 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
     w.items = (int4*)(base + L.items);
     w.partial = (int32_t*)(base + L.partial);
     w.recs = (uint16_t*)(base + L.recs);
+    w.toff = (uint16_t*)(base + L.toff);
     w.trace = (PassRecord*)(base + L.trace);
 
     max_pass = pass_bound(n, eps_num, eps_den);
@@ -1018,7 +1100,8 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
     DSG_HIP(log.begin(kKindInit));
     k_init_state<<<1, 64, 0, s>>>(w, g->row_ptr, n, m, eps_num, eps_den, max_pass,
                                   std::min(trace_cap, kTraceCap), (int32_t)part_stride(n),
-                                  (int32_t)items_cap);
+                                  (int32_t)items_cap,
+                                  launch && (launch->flags & DSG_LAUNCH_BIN_REGIONS) ? 1 : 0);
     k_init<<<init_grid, kBlock, 0, s>>>(w, g->row_ptr, n);
     DSG_HIP(hipGetLastError());
     DSG_HIP(log.end());

@@ -46,7 +46,11 @@ class PassTrace(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("mark_grid", _I32), ("walk_grid", _I32), ("pass_batch", _I32),
-                ("reserved", _I32)]
+                ("flags", _I32)]
+
+
+#: dsg_launch.flags bit: keep degree-update records in per-bin regions
+LAUNCH_BIN_REGIONS = 1
 
 
 class Profile(ctypes.Structure):
@@ -193,7 +197,8 @@ def peel(row_ptr, col_idx, eps=(1, 10), *, m: int | None = None, extract: bool =
     ln = None
     if launch:
         ln = Launch(int(launch.get("mark_grid", 0)), int(launch.get("walk_grid", 0)),
-                    int(launch.get("pass_batch", 0)), 0)
+                    int(launch.get("pass_batch", 0)),
+                    LAUNCH_BIN_REGIONS if launch.get("bin_regions") else 0)
     prof = Profile() if profile else None
     res = Result()
     with torch.cuda.device(dev):

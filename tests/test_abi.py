@@ -65,9 +65,12 @@ def test_workspace_bytes():
     h = dsg.lib()
     small = h.dsg_workspace_bytes(1000, 5000)
     big = h.dsg_workspace_bytes(1 << 24, 261_000_000)
-    # about 28 n + 4 m bytes, plus one partial-count row per apply work item
+    # about 28 n + 4 m bytes, plus the per-tile bin-offset table (2 B per walk
+    # tile per bin) and one partial-count row per degree-update work item
     assert 28 * 1000 + 4 * 5000 <= small < 28 * 1000 + 4 * 5000 + 2_000_000
-    assert 28 * (1 << 24) + 4 * 261_000_000 <= big < 29 * (1 << 24) + 4 * 261_000_000 + 200_000_000
+    tile_table = 2 * (2 * 261_000_000 // 2048 + 2) * 514
+    assert 28 * (1 << 24) + 4 * 261_000_000 <= big
+    assert big < 29 * (1 << 24) + 4 * 261_000_000 + tile_table + 200_000_000
     assert h.dsg_workspace_bytes(-1, 0) == 0
     assert h.dsg_workspace_bytes(2**31, 0) == 0
     assert h.dsg_workspace_bytes(10, 2**30) == 0

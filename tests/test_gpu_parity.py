@@ -101,6 +101,7 @@ def test_config_rmat20(dsg, eps):
     """R-MAT scale 20, edge factor 16, (a,b,c,d) = (.57,.19,.19,.05)."""
     g = _rmat20()
     check(g, eps)
+    check(g, eps, launch={"bin_regions": True})
 
 
 _cache = {}
@@ -115,6 +116,7 @@ def _rmat20():
 @pytest.mark.parametrize("launch", [
     {"walk_grid": 1}, {"walk_grid": 3, "mark_grid": 1}, {"walk_grid": 64, "mark_grid": 7},
     {"pass_batch": 1}, {"pass_batch": 2, "walk_grid": 1000}, {"mark_grid": 5000},
+    {"bin_regions": True}, {"bin_regions": True, "walk_grid": 5, "pass_batch": 1},
 ])
 def test_launch_shape_does_not_change_results(dsg, launch):
     g = inputs.chung_lu(200_000, 24, 2.2, 12)
