@@ -25,6 +25,7 @@ constexpr int kBinWidth = 1 << kBinShift;        // 32768 ranks: 128 KB of LDS c
 constexpr int kNbLds = 1024;                     // bins the walk can stage in LDS
 constexpr int kWaveAggBins = 8;                  // up to this many bins, slots per wave
 constexpr int kApplyBlock = 1024;                // threads of an apply workgroup
+constexpr int kApplyBatch = 8;                   // record loads per lane before counting
 constexpr int64_t kChunkMin = 8192;              // least records per apply work item
 constexpr int64_t kTargetItems = 512;            // apply work items aimed for per pass
 

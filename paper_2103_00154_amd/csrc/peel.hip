@@ -178,32 +178,58 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
 
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t base = t * kMarkTile + (int64_t)threadIdx.x * kMarkItems;
+        // 1. loads: ids and degrees of this thread's entries
+        int32_t vv[kMarkItems], dd[kMarkItems];
+        if (!lin) {
+            int32_t r[kMarkItems + 1];
+#pragma unroll
+            for (int j = 0; j <= kMarkItems; ++j) r[j] = base + j <= S ? rp[base + j] : 0;
+#pragma unroll
+            for (int j = 0; j < kMarkItems; ++j) {
+                vv[j] = base + j < S ? (int32_t)(base + j) : -1;
+                dd[j] = r[j + 1] - r[j];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kMarkItems; ++j) {
+                const bool in = base + j < S;
+                vv[j] = in ? lin[base + j] : -1;
+                dd[j] = in ? din[base + j] : 0;
+            }
+        }
+        int32_t ll[kMarkItems];
+#pragma unroll
+        for (int j = 0; j < kMarkItems; ++j) {
+            const bool ok = (uint64_t)(int64_t)vv[j] < (uint64_t)n;
+            if (!ok) vv[j] = -1;
+            // row length of a failure with degree > 0 (pass 1: the degree itself)
+            ll[j] = (!lin || !ok || dd[j] > T || dd[j] <= 0) ? dd[j] : rp[vv[j] + 1] - rp[vv[j]];
+        }
+        // 2. decisions, removal passes and live bits
         uint32_t cA = 0, cL = 0, cE = 0, cDr = 0, cDs = 0;
         uint32_t wi = 0xFFFFFFFFu, wm = 0;
 #pragma unroll
         for (int j = 0; j < kMarkItems; ++j) {
-            const int64_t idx = base + j;
-            const int32_t v = idx < S ? (lin ? lin[idx] : (int32_t)idx) : -1;
-            if ((uint64_t)(int64_t)v < (uint64_t)n) {
-                const int32_t d = pass == 1 ? rp[v + 1] - rp[v] : din[idx];
-                if (d <= T) {
-                    w.removed_at[v] = pass;
-                    const uint32_t word = (uint32_t)v >> 5;
-                    if (word != wi) {
-                        if (wm) atomicAnd(&w.dir[wi].x, ~wm);
-                        wi = word;
-                        wm = 0;
-                    }
-                    wm |= 1u << (v & 31);
-                    cDr += (uint32_t)d;
-                    if (d > 0) {
-                        ++cA;
-                        cE += (uint32_t)(rp[v + 1] - rp[v]);
-                    }
-                } else {
-                    ++cL;
-                    cDs += (uint32_t)d;
+            const int32_t v = vv[j];
+            if (v < 0) continue;
+            const int32_t d = dd[j];
+            if (d <= T) {
+                w.removed_at[v] = pass;
+                const uint32_t word = (uint32_t)v >> 5;
+                if (word != wi) {
+                    if (wm) atomicAnd(&w.dir[wi].x, ~wm);
+                    wi = word;
+                    wm = 0;
                 }
+                wm |= 1u << (v & 31);
+                cDr += (uint32_t)d;
+                if (d > 0) {
+                    ++cA;
+                    cE += (uint32_t)ll[j];
+                }
+            } else {
+                ++cL;
+                cDs += (uint32_t)d;
             }
         }
         if (wm) atomicAnd(&w.dir[wi].x, ~wm);
@@ -238,6 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(Work w, int32_t mode, int
     const int64_t lo = std::min<int64_t>(nt, per * threadIdx.x);
     const int64_t hi = std::min<int64_t>(nt, lo + per);
     int64_t a = 0, l = 0, e = 0, dr = 0, ds = 0;
+#pragma unroll 8
     for (int64_t i = lo; i < hi; ++i) {
         const int4 c = w.tiles[2 * i];
         a += c.x;
@@ -253,6 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(Work w, int32_t mode, int
     int64_t pe = block_excl_sum(e, red, &te);
     int64_t pds = block_excl_sum(ds, red, &tds);
     const int64_t tdr = block_sum(dr, red);
+#pragma unroll 8
     for (int64_t i = lo; i < hi; ++i) {
         const int4 c = w.tiles[2 * i];
         const int32_t cds = mode == 0 ? w.tiles[2 * i + 1].x : 0;
@@ -308,28 +336,47 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
         int32_t vv[kMarkItems];
         int32_t dd[kMarkItems];
         int32_t ll[kMarkItems];
+        int32_t rs[kMarkItems];  // CSR row start of every entry
+        if (!lin) {
+            int32_t r[kMarkItems + 1];
+#pragma unroll
+            for (int j = 0; j <= kMarkItems; ++j) r[j] = base + j <= S ? rp[base + j] : 0;
+#pragma unroll
+            for (int j = 0; j < kMarkItems; ++j) {
+                vv[j] = base + j < S ? (int32_t)(base + j) : -1;
+                dd[j] = r[j + 1] - r[j];
+                rs[j] = r[j];
+                ll[j] = dd[j];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kMarkItems; ++j) {
+                const bool in = base + j < S;
+                vv[j] = in ? lin[base + j] : -1;
+                dd[j] = in ? din[base + j] : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < kMarkItems; ++j) {
+                const bool need = (uint64_t)(int64_t)vv[j] < (uint64_t)n && dd[j] <= T && dd[j] > 0;
+                rs[j] = need ? rp[vv[j]] : 0;
+                ll[j] = need ? rp[vv[j] + 1] - rs[j] : 0;
+            }
+        }
         uint32_t cA = 0, cL = 0, cE = 0, cDs = 0;
 #pragma unroll
         for (int j = 0; j < kMarkItems; ++j) {
-            const int64_t idx = base + j;
-            vv[j] = -1;
-            dd[j] = 0;
-            ll[j] = 0;
-            const int32_t v = idx < S ? (lin ? lin[idx] : (int32_t)idx) : -1;
-            if ((uint64_t)(int64_t)v < (uint64_t)n) {
-                const int32_t d = pass == 1 ? rp[v + 1] - rp[v] : din[idx];
-                vv[j] = v;
-                dd[j] = d;
-                if (d <= T) {
-                    if (d > 0) {
-                        ll[j] = rp[v + 1] - rp[v];
-                        ++cA;
-                        cE += (uint32_t)ll[j];
-                    }
-                } else {
-                    ++cL;
-                    cDs += (uint32_t)d;
+            if ((uint64_t)(int64_t)vv[j] >= (uint64_t)n) {
+                vv[j] = -1;
+                continue;
+            }
+            if (dd[j] <= T) {
+                if (dd[j] > 0) {
+                    ++cA;
+                    cE += (uint32_t)ll[j];
                 }
+            } else {
+                ++cL;
+                cDs += (uint32_t)dd[j];
             }
         }
         // the element before this thread's first one decides word leadership
@@ -354,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
             prev = v;
             if (dd[j] <= T) {
                 if (dd[j] > 0 && pA < n) {
-                    w.arow[pA] = rp[v];
+                    w.arow[pA] = rs[j];
                     w.aoff[pA] = (int32_t)pE;
                     const int64_t len = ll[j];
                     // walk tiles whose first entry lies in [pE, pE + len)
@@ -461,11 +508,12 @@ __device__ void finish_pass(const Work& w, int32_t* s_flag, int32_t* red) {
         for (int32_t b = threadIdx.x; b < nb; b += kBlock)
             w.bin_items[b] = make_int2((int)(b * ipb), total_a <= cap_a ? (int)ipb : 0);
         if (threadIdx.x == 0) {
-            // lanes per (tile, bin) run in k_apply: about half the mean run
+            // lanes per (tile, bin) run in k_apply: one batch of loads per
+            // lane covers a mean run, so many runs are in flight per workgroup
             const int64_t runs = std::max<int64_t>(1, ntiles * nb);
             const int64_t mean = (int64_t)atomic_load_u64(&st->cross) / runs;
             int32_t lanes = 4;
-            while (lanes < 64 && 2 * lanes < mean) lanes *= 2;
+            while (lanes < 64 && kApplyBatch * lanes < mean) lanes *= 2;
             st->apply_lanes = lanes;
             if (total_a > cap_a) {  // cannot happen: nb * ipb <= max(nb, kTargetItems)
                 st->status = kStInvariant;
@@ -518,21 +566,32 @@ __device__ void finish_pass(const Work& w, int32_t* s_flag, int32_t* red) {
 }
 
 // ------------------------------------------------------------------ walk
+// All positions are 32-bit: 2m <= INT32_MAX, so every adjacency position,
+// walk offset and tile start fits.
 
-__global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restrict__ rp,
-                                                 const int32_t* __restrict__ ci, int64_t n,
-                                                 int64_t nnz) {
+// popcount of `mask` over the lanes below this one
+__device__ inline int32_t lanes_below(unsigned long long mask) {
+    return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                              __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restrict__ ci,
+                                                 uint32_t n, uint32_t nnz) {
     DevState* st = w.st;
     if (st->done) return;
-    const int64_t nA = st->nA;
-    const int64_t total = st->edges;
+    const int32_t nA = (int32_t)st->nA;
+    const uint32_t total = (uint32_t)st->edges;
     // no survivor: no decrement is possible and the rows need no walk
-    const int64_t ntiles = st->nL > 0 ? st->n_tiles_walk : 0;
+    const int32_t ntiles = st->nL > 0 ? st->n_tiles_walk : 0;
     const int32_t nb = st->nbins;
     const bool lds_bins = st->walk_mode == 0;
+    const bool wave_slots = nb <= kWaveAggBins;
     const uint2* __restrict__ dir = w.dir;
     int32_t* __restrict__ bin_cur = w.bin_cur;
     uint16_t* __restrict__ recs = w.recs;
+    const int32_t* __restrict__ aoff = w.aoff;
+    const int32_t* __restrict__ arow = w.arow;
+    const int tid = threadIdx.x;
 
     __shared__ __align__(16) int32_t own[kWalkTile];
     __shared__ int32_t bas[kWalkTile + 1];
@@ -543,89 +602,82 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
     __shared__ int32_t s_keep;
 
     uint32_t cross = 0;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int64_t e0 = t * kWalkTile;
-        const int32_t len = (int32_t)std::min<int64_t>(kWalkTile, total - e0);
-        const int64_t i0 = w.tile_first[t];
-        const int64_t ihi = (t + 1 < ntiles) ? (int64_t)w.tile_first[t + 1] : nA - 1;
+    for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t e0 = (uint32_t)t * kWalkTile;
+        const int32_t len = (int32_t)min((uint32_t)kWalkTile, total - e0);
+        const int32_t i0 = w.tile_first[t];
+        const int32_t ihi = (t + 1 < ntiles) ? w.tile_first[t + 1] : nA - 1;
         if (i0 < 0 || ihi >= nA || ihi < i0 || ihi - i0 + 1 > kWalkTile + 1) {
             // cannot happen for a consistent walk list; never index with it
-            if (threadIdx.x == 0) st->status = kStInvariant;
+            if (tid == 0) st->status = kStInvariant;
             continue;
         }
-        const int32_t c = (int32_t)(ihi - i0 + 1);
+        const int32_t c = ihi - i0 + 1;
 
-        for (int p = threadIdx.x; p < kWalkTile; p += kBlock) own[p] = 0;
+        // 1. owner of every entry of the tile: rows start at strictly
+        //    increasing offsets, so a running max over the start marks works
+        int4* own4 = reinterpret_cast<int4*>(own);
+        own4[2 * tid] = make_int4(0, 0, 0, 0);
+        own4[2 * tid + 1] = make_int4(0, 0, 0, 0);
         if (lds_bins)
-            for (int b = threadIdx.x; b < nb; b += kBlock) tcount[b] = 0;
+            for (int b = tid; b < nb; b += kBlock) tcount[b] = 0;
         __syncthreads();
-        for (int i = threadIdx.x; i < c; i += kBlock) {
-            const int64_t a = i0 + i;
-            const int32_t off = w.aoff[a];
-            bas[i] = w.arow[a] - off;
-            const int64_t o = (int64_t)off - e0;
+        for (int32_t i = tid; i < c; i += kBlock) {
+            const int32_t off = aoff[i0 + i];
+            bas[i] = arow[i0 + i] - off;
+            const int32_t o = off - (int32_t)e0;
             if (o < len) own[o > 0 ? o : 0] = i;
         }
         __syncthreads();
         {
-            // inclusive running max of own[] = index of the row owning each entry
-            const int b = threadIdx.x * kWalkItems;
-            int32_t loc[kWalkItems];
-            int32_t run = 0;
-#pragma unroll
-            for (int j = 0; j < kWalkItems; ++j) {
-                run = max(run, own[b + j]);
-                loc[j] = run;
-            }
-            const int32_t carry = block_excl_max(run, red, 0);
-#pragma unroll
-            for (int j = 0; j < kWalkItems; ++j) own[b + j] = max(loc[j], carry);
+            const int4 a = own4[2 * tid], b = own4[2 * tid + 1];
+            int32_t r0 = a.x, r1 = max(r0, a.y), r2 = max(r1, a.z), r3 = max(r2, a.w);
+            int32_t r4 = max(r3, b.x), r5 = max(r4, b.y), r6 = max(r5, b.z), r7 = max(r6, b.w);
+            const int32_t carry = block_excl_max(r7, red, 0);
+            own4[2 * tid] = make_int4(max(r0, carry), max(r1, carry), max(r2, carry), max(r3, carry));
+            own4[2 * tid + 1] =
+                make_int4(max(r4, carry), max(r5, carry), max(r6, carry), max(r7, carry));
         }
         __syncthreads();
+
+        // 2. neighbour ids (coalesced: consecutive lanes, consecutive entries)
         int32_t u[kWalkItems];
 #pragma unroll
         for (int j = 0; j < kWalkItems; ++j) {
-            const int p = j * kBlock + threadIdx.x;
-            u[j] = -1;
-            if (p < len) {
-                const int64_t pos = (int64_t)bas[own[p]] + e0 + p;
-                if ((uint64_t)pos < (uint64_t)nnz) {
-                    const int32_t x = __builtin_nontemporal_load(&ci[pos]);
-                    u[j] = (int64_t)(uint32_t)x < n ? x : -1;  // ids outside 0..n-1 are ignored
-                }
-            }
+            const int p = j * kBlock + tid;
+            const uint32_t pos = (uint32_t)bas[own[p]] + (e0 + (uint32_t)p);
+            int32_t x = -1;
+            if (p < len && pos < nnz) x = __builtin_nontemporal_load(ci + pos);
+            u[j] = (uint32_t)x < n ? x : -1;  // ids outside 0..n-1 are ignored
         }
-        // survivor rank of every neighbour still present, else -1
+        // 3. survivor rank of every neighbour still present, else -1
         int32_t rk[kWalkItems];
 #pragma unroll
         for (int j = 0; j < kWalkItems; ++j) {
-            rk[j] = -1;
-            if (u[j] >= 0) {
-                const uint2 d = dir[u[j] >> 5];
-                const uint32_t bit = 1u << (u[j] & 31);
-                if (d.x & bit) rk[j] = (int32_t)(d.y + __popc(d.x & (bit - 1u)));
-            }
+            const uint32_t x = (uint32_t)max(u[j], 0);
+            const uint2 d = dir[x >> 5];
+            const uint32_t bit = 1u << (x & 31);
+            rk[j] = (u[j] >= 0 && (d.x & bit)) ? (int32_t)(d.y + __popc(d.x & (bit - 1u))) : -1;
         }
-        int32_t slot[kWalkItems];
         if (lds_bins) {
-            if (nb <= kWaveAggBins) {
-                // few bins: one LDS atomic per (wave, bin); lanes of a bin take
-                // consecutive slots, so their records are stored contiguously
+            // 4. slot of every record inside its (tile, bin) group
+            int32_t slot[kWalkItems];
+            if (wave_slots) {
+                // one LDS atomic per (wave, bin); a bin's lanes take consecutive slots
                 const int lane = lane_id();
-                const unsigned long long below = (1ull << lane) - 1ull;
 #pragma unroll
                 for (int j = 0; j < kWalkItems; ++j) {
                     const int32_t my_bin = rk[j] >= 0 ? rk[j] >> kBinShift : -1;
                     unsigned long long active = __ballot(my_bin >= 0);
                     slot[j] = 0;
                     while (active) {
-                        const int leader = __ffsll((long long)active) - 1;
-                        const int32_t b = __shfl(my_bin, leader, 64);
+                        const int leader = (int)__builtin_ctzll(active);
+                        const int32_t b = __builtin_amdgcn_readlane(my_bin, leader);
                         const unsigned long long same = __ballot(my_bin == b);
                         int32_t at = 0;
                         if (lane == leader) at = atomicAdd(&tcount[b], (int32_t)__popcll(same));
-                        at = __shfl(at, leader, 64);
-                        if (my_bin == b) slot[j] = at + (int32_t)__popcll(same & below);
+                        at = __builtin_amdgcn_readlane(at, leader);
+                        if (my_bin == b) slot[j] = at + lanes_below(same);
                         active &= ~same;
                     }
                 }
@@ -636,25 +688,26 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
             }
             __syncthreads();
             {
-                // this tile's records go to its own region, grouped by bin:
-                // exclusive prefix of the bin counts, also kept in the table
+                // 5. the tile's records go to its own region, grouped by bin:
+                //    exclusive prefix of the bin counts, also kept in the table
                 const int q = (nb + kBlock - 1) / kBlock;
-                const int b0 = min(nb, q * (int)threadIdx.x), b1 = min(nb, b0 + q);
+                const int b0 = min(nb, q * tid), b1 = min(nb, b0 + q);
                 int32_t s = 0;
                 for (int b = b0; b < b1; ++b) s += tcount[b];
                 int32_t all;
                 int32_t at = block_excl_sum(s, red, &all);
-                uint16_t* __restrict__ to = w.toff + t * (int64_t)(nb + 1);
+                uint16_t* __restrict__ to = w.toff + (int64_t)t * (nb + 1);
                 for (int b = b0; b < b1; ++b) {
                     const int32_t k = tcount[b];
                     tcount[b] = at;
                     to[b] = (uint16_t)at;
                     at += k;
                 }
-                if (threadIdx.x == 0) to[nb] = (uint16_t)all;
+                if (tid == 0) to[nb] = (uint16_t)all;
             }
             __syncthreads();
-            uint16_t* __restrict__ tr = recs + t * (int64_t)kWalkTile;
+            // 6. records
+            uint16_t* __restrict__ tr = recs + (int64_t)t * kWalkTile;
 #pragma unroll
             for (int j = 0; j < kWalkItems; ++j) {
                 if (rk[j] >= 0) {
@@ -675,7 +728,7 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
         __syncthreads();
     }
     const unsigned long long bc = block_sum((unsigned long long)cross, redc);
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         if (bc) atomicAdd(&st->cross, bc);
         __threadfence();
         const uint32_t tk = atomicAdd(&st->ticket, 1u);
@@ -710,12 +763,39 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply(Work w) {
         for (int i = threadIdx.x; i < ranks; i += kApplyBlock) cnt[i] = 0;
         __syncthreads();
         if (mode == 0) {
-            // groups of `lanes` threads walk one tile's run of this bin's records
-            for (int64_t tt = (int64_t)item.y + grp; tt < item.z; tt += groups) {
+            // groups of `lanes` threads walk one tile's run of this bin's
+            // records; the next tile's run bounds load while this run counts
+            int64_t tt = (int64_t)item.y + grp;
+            int32_t s = 0, e = 0;
+            if (tt < item.z) {
                 const uint16_t* __restrict__ o = w.toff + tt * tstride + item.x;
-                const int32_t s = o[0], e = o[1];
+                s = o[0];
+                e = o[1];
+            }
+            while (tt < item.z) {
+                const int64_t tn = tt + groups;
+                int32_t sn = 0, en = 0;
+                if (tn < item.z) {
+                    const uint16_t* __restrict__ o = w.toff + tn * tstride + item.x;
+                    sn = o[0];
+                    en = o[1];
+                }
                 const uint16_t* __restrict__ r = recs + tt * (int64_t)kWalkTile;
-                for (int32_t x = s + sub; x < e; x += lanes) atomicAdd(&cnt[r[x]], 1);
+                for (int32_t x0 = s + sub; x0 < e; x0 += kApplyBatch * lanes) {
+                    // issue the batch's loads before any count
+                    uint32_t v[kApplyBatch];
+#pragma unroll
+                    for (int k = 0; k < kApplyBatch; ++k) {
+                        const int32_t x = x0 + k * lanes;
+                        v[k] = x < e ? (uint32_t)r[x] : 0xFFFFFFFFu;
+                    }
+#pragma unroll
+                    for (int k = 0; k < kApplyBatch; ++k)
+                        if (v[k] != 0xFFFFFFFFu) atomicAdd(&cnt[v[k]], 1);
+                }
+                tt = tn;
+                s = sn;
+                e = en;
             }
         } else {
             int64_t e = (int64_t)item.y + threadIdx.x;
@@ -1116,7 +1196,7 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
             DSG_HIP(hipGetLastError());
             DSG_HIP(log.end());
             DSG_HIP(log.begin(kKindWalk));
-            k_walk<<<walk_grid, kBlock, 0, s>>>(w, g->row_ptr, g->col_idx, n, 2 * m);
+            k_walk<<<walk_grid, kBlock, 0, s>>>(w, g->col_idx, (uint32_t)n, (uint32_t)(2 * m));
             DSG_HIP(hipGetLastError());
             DSG_HIP(log.end());
             DSG_HIP(log.begin(kKindApply));
