@@ -11,8 +11,9 @@ constexpr int kBlock = 256;                      // threads per workgroup (4 wav
 constexpr int kWaves = kBlock / 64;
 constexpr int kMarkItems = 8;                    // live-list entries per thread
 constexpr int kMarkTile = kBlock * kMarkItems;   // live-list entries per tile
-constexpr int kWalkItems = 8;                    // adjacency entries per thread
+constexpr int kWalkItems = 16;                   // adjacency entries per thread
 constexpr int kWalkTile = kBlock * kWalkItems;   // adjacency entries per tile
+static_assert(kWalkItems % 4 == 0, "the owner scan moves int4 words");
 constexpr int kTraceCap = 4096;                  // device trace records
 constexpr int32_t kNever = INT32_MAX;            // removed_at of a vertex still present
 
@@ -24,6 +25,7 @@ constexpr int kBinShift = 15;
 constexpr int kBinWidth = 1 << kBinShift;        // 32768 ranks: 128 KB of LDS counters
 constexpr int kNbLds = 1024;                     // bins the walk can stage in LDS
 constexpr int kWaveAggBins = 8;                  // up to this many bins, slots per wave
+constexpr int kScanBlock = 256;                  // threads of the tile-scan workgroup
 constexpr int kApplyBlock = 1024;                // threads of an apply workgroup
 constexpr int kApplyBatch = 8;                   // record loads per lane before counting
 constexpr int64_t kChunkMin = 8192;              // least records per apply work item
@@ -77,6 +79,7 @@ struct alignas(256) DevState {
     int32_t toff_stride;  // entries per tile in the tile-offset table (bins + 1)
     int32_t force_bins;   // 1: always use bin regions (launch flag)
     int32_t apply_lanes;  // lanes that share one tile's run in k_apply (4..64)
+    int32_t reduce_lanes; // lanes that share one rank in k_reduce (1..16)
 };
 
 struct PassRecord {
@@ -126,16 +129,16 @@ __device__ inline int32_t wave_incl_max(int32_t x) {
     return x;
 }
 
-// Block-wide exclusive sum; *total receives the block sum.  `red` holds
-// kWaves elements of LDS.  Contains two barriers.
-template <typename T>
+// Block-wide exclusive sum over NW waves; *total receives the block sum.
+// `red` holds NW elements of LDS.  Contains two barriers.
+template <typename T, int NW = kWaves>
 __device__ inline T block_excl_sum(T x, T* red, T* total) {
     const T incl = wave_incl_sum(x);
     if (lane_id() == 63) red[wave_id()] = incl;
     __syncthreads();
     T before = 0, all = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
+    for (int w = 0; w < NW; ++w) {
         const T v = red[w];
         before += (w < wave_id()) ? v : T(0);
         all += v;
@@ -145,15 +148,15 @@ __device__ inline T block_excl_sum(T x, T* red, T* total) {
     return before + incl - x;
 }
 
-// Block-wide sum returned to every thread.  Two barriers.
-template <typename T>
+// Block-wide sum over NW waves, returned to every thread.  Two barriers.
+template <typename T, int NW = kWaves>
 __device__ inline T block_sum(T x, T* red) {
     x = wave_sum(x);
     if (lane_id() == 0) red[wave_id()] = x;
     __syncthreads();
     T all = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) all += red[w];
+    for (int w = 0; w < NW; ++w) all += red[w];
     __syncthreads();
     return all;
 }

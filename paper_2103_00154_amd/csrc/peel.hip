@@ -6,7 +6,8 @@
 //
 //   k_mark_count    part 1, the failure test, over the live list L_{k-1}
 //                   and its dense degree array: every vertex whose degree is
-//                   <= T_k fails: removed_at = k, live bit cleared.  Per tile of the live list it records the
+//                   <= T_k fails: removed_at = k, live bit cleared (pass 1
+//                   writes removed_at and the live bits of every vertex).  Per tile of the live list it records the
 //                   failures with degree > 0, the survivors, the CSR row
 //                   length of the former and the degree sums of both groups.
 //   k_scan_tiles    exclusive prefix of the tile records (one workgroup).
@@ -29,7 +30,7 @@
 //                   in LDS (one counter per rank of the bin) and writes the
 //                   counts as one partial row.
 //   k_reduce        subtracts every bin's partial rows from the survivors'
-//                   degrees (64 ranks x 16 item lanes per workgroup).
+//                   degrees (1 to 16 lanes per rank, by the rows per bin).
 //
 // The "barrier synchronization" between the two parts of Algorithm 1 is the
 // kernel boundary between k_mark_scatter and k_walk.  The degree decrements
@@ -99,6 +100,22 @@ __device__ inline int32_t* deg_out(const Work& w, int32_t pass) {
     return (pass & 1) ? w.deg1 : w.deg0;
 }
 
+// out[j] = p[base + j] for base + j < lim, else `fill`; two 16-byte loads
+// when the span is whole and 16-byte aligned.
+__device__ inline void load8(const int32_t* __restrict__ p, int64_t base, int64_t lim,
+                             int32_t fill, int32_t out[8]) {
+    const int32_t* q = p + base;
+    if (base + 8 <= lim && ((uintptr_t)q & 15u) == 0) {
+        const int4 a = reinterpret_cast<const int4*>(q)[0];
+        const int4 b = reinterpret_cast<const int4*>(q)[1];
+        out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = a.w;
+        out[4] = b.x; out[5] = b.y; out[6] = b.z; out[7] = b.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) out[j] = base + j < lim ? q[j] : fill;
+    }
+}
+
 // ------------------------------------------------------------------ init
 // Two kernels so that the per-vertex kernel can flag a bad row_ptr without
 // racing the initialisation of the state.
@@ -136,6 +153,7 @@ __global__ void k_init_state(Work w, const int32_t* __restrict__ rp, int64_t n, 
     st->toff_stride = 1;
     st->force_bins = force_bins;
     st->apply_lanes = 64;
+    st->reduce_lanes = 16;
     if (rp[0] != 0 || (int64_t)rp[n] != 2 * m) {
         st->status = kStBadRowPtr;
         st->done = 1;
@@ -146,10 +164,9 @@ __global__ __launch_bounds__(kBlock) void k_init(Work w, const int32_t* __restri
                                                  int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     bool bad = false;
-    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += stride) {
+    // removed_at needs no initialisation: pass 1 writes every entry
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += stride)
         bad |= rp[v + 1] < rp[v];
-        w.removed_at[v] = kNever;
-    }
     const int64_t nw = (n + 31) >> 5;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nw; i += stride) {
         const int64_t left = n - i * 32;
@@ -179,23 +196,20 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t base = t * kMarkTile + (int64_t)threadIdx.x * kMarkItems;
         // 1. loads: ids and degrees of this thread's entries
+        static_assert(kMarkItems == 8, "8-wide loads");
         int32_t vv[kMarkItems], dd[kMarkItems];
         if (!lin) {
-            int32_t r[kMarkItems + 1];
-#pragma unroll
-            for (int j = 0; j <= kMarkItems; ++j) r[j] = base + j <= S ? rp[base + j] : 0;
+            int32_t r[kMarkItems];
+            load8(rp, base, S + 1, 0, r);
+            const int32_t r8 = base + 8 <= S ? rp[base + 8] : 0;
 #pragma unroll
             for (int j = 0; j < kMarkItems; ++j) {
                 vv[j] = base + j < S ? (int32_t)(base + j) : -1;
-                dd[j] = r[j + 1] - r[j];
+                dd[j] = (j + 1 < kMarkItems ? r[j + 1] : r8) - r[j];
             }
         } else {
-#pragma unroll
-            for (int j = 0; j < kMarkItems; ++j) {
-                const bool in = base + j < S;
-                vv[j] = in ? lin[base + j] : -1;
-                dd[j] = in ? din[base + j] : 0;
-            }
+            load8(lin, base, S, -1, vv);
+            load8(din, base, S, 0, dd);
         }
         int32_t ll[kMarkItems];
 #pragma unroll
@@ -208,20 +222,25 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
         // 2. decisions, removal passes and live bits
         uint32_t cA = 0, cL = 0, cE = 0, cDr = 0, cDs = 0;
         uint32_t wi = 0xFFFFFFFFu, wm = 0;
+        uint32_t gone8 = 0;  // pass 1: bit j set when entry j fails
 #pragma unroll
         for (int j = 0; j < kMarkItems; ++j) {
             const int32_t v = vv[j];
             if (v < 0) continue;
             const int32_t d = dd[j];
             if (d <= T) {
-                w.removed_at[v] = pass;
-                const uint32_t word = (uint32_t)v >> 5;
-                if (word != wi) {
-                    if (wm) atomicAnd(&w.dir[wi].x, ~wm);
-                    wi = word;
-                    wm = 0;
+                if (lin) {
+                    w.removed_at[v] = pass;
+                    const uint32_t word = (uint32_t)v >> 5;
+                    if (word != wi) {
+                        if (wm) atomicAnd(&w.dir[wi].x, ~wm);
+                        wi = word;
+                        wm = 0;
+                    }
+                    wm |= 1u << (v & 31);
+                } else {
+                    gone8 |= 1u << j;
                 }
-                wm |= 1u << (v & 31);
                 cDr += (uint32_t)d;
                 if (d > 0) {
                     ++cA;
@@ -232,7 +251,28 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
                 cDs += (uint32_t)d;
             }
         }
-        if (wm) atomicAnd(&w.dir[wi].x, ~wm);
+        if (lin) {
+            if (wm) atomicAnd(&w.dir[wi].x, ~wm);
+        } else {
+            // pass 1: ids base..base+7 lie in one 32-vertex word that only the
+            // four consecutive lanes (tid & ~3) .. (tid | 3) touch; they merge
+            // their masks and one of them stores the word
+            static_assert(kMarkItems == 8, "four lanes per 32-vertex word");
+            if (base < S) {
+#pragma unroll
+                for (int j = 0; j < kMarkItems; ++j)
+                    if (base + j < S) w.removed_at[base + j] = (gone8 >> j & 1u) ? pass : kNever;
+            }
+            uint32_t gone = gone8 << (8 * (threadIdx.x & 3));
+            gone |= __shfl_xor(gone, 1, 64);
+            gone |= __shfl_xor(gone, 2, 64);
+            const int64_t wbase = base & ~(int64_t)31;
+            if ((threadIdx.x & 3) == 0 && wbase < S) {
+                const int64_t left = n - wbase;
+                const uint32_t valid = left >= 32 ? 0xFFFFFFFFu : ((1u << left) - 1u);
+                w.dir[wbase >> 5].x = valid & ~gone;
+            }
+        }
         const uint32_t tA = block_sum(cA, red);
         const uint32_t tL = block_sum(cL, red);
         const uint32_t tE = block_sum(cE, red);
@@ -251,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
 //         failures' degree sum is only totalled).
 // mode 1: the extract tiles over 0..n-1 (component x).
 
-__global__ __launch_bounds__(kBlock) void k_scan_tiles(Work w, int32_t mode, int64_t n) {
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode, int64_t n) {
     DevState* st = w.st;
     if (mode == 0) {
         if (st->done) return;
@@ -260,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(Work w, int32_t mode, int
     }
     const int64_t items = mode == 0 ? st->S : n;
     const int64_t nt = (items + kMarkTile - 1) / kMarkTile;
-    const int64_t per = (nt + kBlock - 1) / kBlock;
+    const int64_t per = (nt + kScanBlock - 1) / kScanBlock;
     const int64_t lo = std::min<int64_t>(nt, per * threadIdx.x);
     const int64_t hi = std::min<int64_t>(nt, lo + per);
     int64_t a = 0, l = 0, e = 0, dr = 0, ds = 0;
@@ -273,13 +313,13 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(Work w, int32_t mode, int
         dr += (uint32_t)c.w;
         if (mode == 0) ds += (uint32_t)w.tiles[2 * i + 1].x;
     }
-    __shared__ int64_t red[kWaves];
+    __shared__ int64_t red[kScanBlock / 64];
     int64_t ta, tl, te, tds;
-    int64_t pa = block_excl_sum(a, red, &ta);
-    int64_t pl = block_excl_sum(l, red, &tl);
-    int64_t pe = block_excl_sum(e, red, &te);
-    int64_t pds = block_excl_sum(ds, red, &tds);
-    const int64_t tdr = block_sum(dr, red);
+    int64_t pa = block_excl_sum<int64_t, kScanBlock / 64>(a, red, &ta);
+    int64_t pl = block_excl_sum<int64_t, kScanBlock / 64>(l, red, &tl);
+    int64_t pe = block_excl_sum<int64_t, kScanBlock / 64>(e, red, &te);
+    int64_t pds = block_excl_sum<int64_t, kScanBlock / 64>(ds, red, &tds);
+    const int64_t tdr = block_sum<int64_t, kScanBlock / 64>(dr, red);
 #pragma unroll 8
     for (int64_t i = lo; i < hi; ++i) {
         const int4 c = w.tiles[2 * i];
@@ -338,23 +378,19 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
         int32_t ll[kMarkItems];
         int32_t rs[kMarkItems];  // CSR row start of every entry
         if (!lin) {
-            int32_t r[kMarkItems + 1];
-#pragma unroll
-            for (int j = 0; j <= kMarkItems; ++j) r[j] = base + j <= S ? rp[base + j] : 0;
+            int32_t r[kMarkItems];
+            load8(rp, base, S + 1, 0, r);
+            const int32_t r8 = base + 8 <= S ? rp[base + 8] : 0;
 #pragma unroll
             for (int j = 0; j < kMarkItems; ++j) {
                 vv[j] = base + j < S ? (int32_t)(base + j) : -1;
-                dd[j] = r[j + 1] - r[j];
+                dd[j] = (j + 1 < kMarkItems ? r[j + 1] : r8) - r[j];
                 rs[j] = r[j];
                 ll[j] = dd[j];
             }
         } else {
-#pragma unroll
-            for (int j = 0; j < kMarkItems; ++j) {
-                const bool in = base + j < S;
-                vv[j] = in ? lin[base + j] : -1;
-                dd[j] = in ? din[base + j] : 0;
-            }
+            load8(lin, base, S, -1, vv);
+            load8(din, base, S, 0, dd);
 #pragma unroll
             for (int j = 0; j < kMarkItems; ++j) {
                 const bool need = (uint64_t)(int64_t)vv[j] < (uint64_t)n && dd[j] <= T && dd[j] > 0;
@@ -515,6 +551,10 @@ __device__ void finish_pass(const Work& w, int32_t* s_flag, int32_t* red) {
             int32_t lanes = 4;
             while (lanes < 64 && kApplyBatch * lanes < mean) lanes *= 2;
             st->apply_lanes = lanes;
+            // lanes per rank in k_reduce: about four partial rows per lane
+            int32_t rl = 1;
+            while (rl < 16 && 4 * rl < ipb) rl *= 2;
+            st->reduce_lanes = rl;
             if (total_a > cap_a) {  // cannot happen: nb * ipb <= max(nb, kTargetItems)
                 st->status = kStInvariant;
                 st->done = 1;
@@ -526,6 +566,7 @@ __device__ void finish_pass(const Work& w, int32_t* s_flag, int32_t* red) {
         return;
     }
     // records sit in bin regions: split every bin into items of <= chunk records
+    if (threadIdx.x == 0) st->reduce_lanes = 16;
     const int64_t ch = st->chunk;
     const int32_t per = (nb + kBlock - 1) / kBlock;
     const int32_t lo = std::min<int32_t>(nb, per * (int32_t)threadIdx.x);
@@ -596,6 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
     __shared__ __align__(16) int32_t own[kWalkTile];
     __shared__ int32_t bas[kWalkTile + 1];
     __shared__ int32_t tcount[kNbLds];  // per-tile bin counts, then their offsets
+    __shared__ int32_t wtot[kWaves][kWaveAggBins];  // per-wave bin counts (few bins)
     __shared__ int32_t red[kWaves];
     __shared__ unsigned long long redc[kWaves];
     __shared__ int32_t s_last;
@@ -616,9 +658,10 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
 
         // 1. owner of every entry of the tile: rows start at strictly
         //    increasing offsets, so a running max over the start marks works
+        constexpr int kQ = kWalkItems / 4;  // int4 words of own[] per thread
         int4* own4 = reinterpret_cast<int4*>(own);
-        own4[2 * tid] = make_int4(0, 0, 0, 0);
-        own4[2 * tid + 1] = make_int4(0, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) own4[kQ * tid + q] = make_int4(0, 0, 0, 0);
         if (lds_bins)
             for (int b = tid; b < nb; b += kBlock) tcount[b] = 0;
         __syncthreads();
@@ -630,13 +673,22 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
         }
         __syncthreads();
         {
-            const int4 a = own4[2 * tid], b = own4[2 * tid + 1];
-            int32_t r0 = a.x, r1 = max(r0, a.y), r2 = max(r1, a.z), r3 = max(r2, a.w);
-            int32_t r4 = max(r3, b.x), r5 = max(r4, b.y), r6 = max(r5, b.z), r7 = max(r6, b.w);
-            const int32_t carry = block_excl_max(r7, red, 0);
-            own4[2 * tid] = make_int4(max(r0, carry), max(r1, carry), max(r2, carry), max(r3, carry));
-            own4[2 * tid + 1] =
-                make_int4(max(r4, carry), max(r5, carry), max(r6, carry), max(r7, carry));
+            int4 q4[kQ];
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) q4[q] = own4[kQ * tid + q];
+            int32_t run = 0;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                q4[q].x = run = max(run, q4[q].x);
+                q4[q].y = run = max(run, q4[q].y);
+                q4[q].z = run = max(run, q4[q].z);
+                q4[q].w = run = max(run, q4[q].w);
+            }
+            const int32_t carry = block_excl_max(run, red, 0);
+#pragma unroll
+            for (int q = 0; q < kQ; ++q)
+                own4[kQ * tid + q] = make_int4(max(q4[q].x, carry), max(q4[q].y, carry),
+                                               max(q4[q].z, carry), max(q4[q].w, carry));
         }
         __syncthreads();
 
@@ -663,25 +715,46 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
             // 4. slot of every record inside its (tile, bin) group
             int32_t slot[kWalkItems];
             if (wave_slots) {
-                // one LDS atomic per (wave, bin); a bin's lanes take consecutive slots
-                const int lane = lane_id();
+                // few bins: ballots give each lane its rank among the wave's
+                // records of its bin (items in order, lanes in order); a
+                // table of per-wave totals then orders the waves
+                int32_t run[kWaveAggBins];
+#pragma unroll
+                for (int b = 0; b < kWaveAggBins; ++b) run[b] = 0;
 #pragma unroll
                 for (int j = 0; j < kWalkItems; ++j) {
                     const int32_t my_bin = rk[j] >= 0 ? rk[j] >> kBinShift : -1;
-                    unsigned long long active = __ballot(my_bin >= 0);
                     slot[j] = 0;
-                    while (active) {
-                        const int leader = (int)__builtin_ctzll(active);
-                        const int32_t b = __builtin_amdgcn_readlane(my_bin, leader);
-                        const unsigned long long same = __ballot(my_bin == b);
-                        int32_t at = 0;
-                        if (lane == leader) at = atomicAdd(&tcount[b], (int32_t)__popcll(same));
-                        at = __builtin_amdgcn_readlane(at, leader);
-                        if (my_bin == b) slot[j] = at + lanes_below(same);
-                        active &= ~same;
+#pragma unroll
+                    for (int b = 0; b < kWaveAggBins; ++b) {
+                        if (b < nb) {
+                            const unsigned long long m = __ballot(my_bin == b);
+                            if (my_bin == b) slot[j] = run[b] + lanes_below(m);
+                            run[b] += (int32_t)__popcll(m);
+                        }
+                    }
+                }
+                if (lane_id() == 0)
+                    for (int b = 0; b < nb; ++b) wtot[wave_id()][b] = run[b];
+                __syncthreads();
+                if (tid < nb) {
+                    int32_t s = 0;
+#pragma unroll
+                    for (int v = 0; v < kWaves; ++v) s += wtot[v][tid];
+                    tcount[tid] = s;
+                }
+#pragma unroll
+                for (int j = 0; j < kWalkItems; ++j) {
+                    if (rk[j] >= 0) {
+                        const int32_t b = rk[j] >> kBinShift;
+                        int32_t before = 0;
+                        for (int v = 0; v < wave_id(); ++v) before += wtot[v][b];
+                        slot[j] += before;
                     }
                 }
             } else {
+                // many bins: one LDS atomic per record; the returns are
+                // independent, so they pipeline
 #pragma unroll
                 for (int j = 0; j < kWalkItems; ++j)
                     slot[j] = rk[j] >= 0 ? atomicAdd(&tcount[rk[j] >> kBinShift], 1) : 0;
@@ -821,37 +894,39 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply(Work w) {
 // degree[r] -= sum of the partial rows of r's bin, for every survivor rank r
 // of the pass just finished.  64 consecutive ranks share a bin.
 
-constexpr int kReduceRanks = 64;
-constexpr int kReduceLanes = kApplyBlock / kReduceRanks;
-
-__global__ __launch_bounds__(kApplyBlock) void k_reduce(Work w) {
+__global__ __launch_bounds__(kBlock) void k_reduce(Work w) {
     const DevState* st = w.st;
     if (st->n_items == 0) return;
     const int64_t nL = st->nL;
     const int32_t stride = st->part_stride;
+    // `lanes` lanes of a wave share one rank (1..16); within the wave the
+    // 64 / lanes ranks are consecutive, so each partial row is read in runs
+    const int lanes = st->reduce_lanes;
     int32_t* __restrict__ deg = deg_in(w, st->pass);  // the pass counter has advanced
-    const int64_t ntasks = (nL + kReduceRanks - 1) / kReduceRanks;
-    const int rl = threadIdx.x % kReduceRanks;
-    const int lane = threadIdx.x / kReduceRanks;
-    __shared__ int32_t part[kReduceLanes][kReduceRanks];
+    const int ranks_per_wave = 64 / lanes;
+    const int64_t per_block = (int64_t)kWaves * ranks_per_wave;
+    const int64_t ntasks = (nL + per_block - 1) / per_block;
+    const int sub = lane_id() / ranks_per_wave;
+    const int rr = lane_id() % ranks_per_wave;
     for (int64_t task = blockIdx.x; task < ntasks; task += gridDim.x) {
-        const int64_t r = task * kReduceRanks + rl;
+        const int64_t r = task * per_block + (int64_t)wave_id() * ranks_per_wave + rr;
         int32_t sum = 0;
         if (r < nL) {
             const int2 bi = w.bin_items[r >> kBinShift];
             const int32_t* __restrict__ p =
                 w.partial + (int64_t)bi.x * stride + (r & (kBinWidth - 1));
-            for (int32_t i = lane; i < bi.y; i += kReduceLanes) sum += p[(int64_t)i * stride];
+            int32_t i = sub;
+            for (; i + 3 * lanes < bi.y; i += 4 * lanes) {
+                const int32_t a = p[(int64_t)i * stride];
+                const int32_t b = p[(int64_t)(i + lanes) * stride];
+                const int32_t c = p[(int64_t)(i + 2 * lanes) * stride];
+                const int32_t d = p[(int64_t)(i + 3 * lanes) * stride];
+                sum += a + b + c + d;
+            }
+            for (; i < bi.y; i += lanes) sum += p[(int64_t)i * stride];
         }
-        part[lane][rl] = sum;
-        __syncthreads();
-        if (lane == 0 && r < nL) {
-            int32_t tot = 0;
-#pragma unroll
-            for (int l = 0; l < kReduceLanes; ++l) tot += part[l][rl];
-            if (tot) deg[r] -= tot;
-        }
-        __syncthreads();
+        for (int off = ranks_per_wave; off < 64; off <<= 1) sum += __shfl_xor(sum, off, 64);
+        if (sub == 0 && r < nL && sum) deg[r] -= sum;
     }
 }
 
@@ -866,10 +941,12 @@ __global__ __launch_bounds__(kBlock) void k_extract_count(Work w, int64_t n) {
     __shared__ uint32_t red[kWaves];
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t base = t * kMarkTile + (int64_t)threadIdx.x * kMarkItems;
+        int32_t ra[kMarkItems];
+        load8(w.removed_at, base, n, 0, ra);
         uint32_t c = 0;
 #pragma unroll
         for (int j = 0; j < kMarkItems; ++j)
-            if (base + j < n && w.removed_at[base + j] > bp) ++c;
+            if (base + j < n && ra[j] > bp) ++c;
         const uint32_t tc = block_sum(c, red);
         if (threadIdx.x == 0) w.tiles[2 * t] = make_int4((int)tc, 0, 0, 0);
     }
@@ -884,10 +961,12 @@ __global__ __launch_bounds__(kBlock) void k_extract_scatter(Work w, int64_t n,
     __shared__ uint32_t red[kWaves];
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t base = t * kMarkTile + (int64_t)threadIdx.x * kMarkItems;
+        int32_t ra[kMarkItems];
+        load8(w.removed_at, base, n, 0, ra);
         uint32_t keep = 0, c = 0;
 #pragma unroll
         for (int j = 0; j < kMarkItems; ++j)
-            if (base + j < n && w.removed_at[base + j] > bp) {
+            if (base + j < n && ra[j] > bp) {
                 keep |= 1u << j;
                 ++c;
             }
@@ -1173,7 +1252,7 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
         apply_grid = (unsigned)std::max<int64_t>(
             1, std::min<int64_t>((int64_t)di.cus * di.apply_blocks_per_cu, items_cap));
         reduce_grid = (unsigned)std::max<int64_t>(
-            1, std::min<int64_t>((int64_t)di.cus * 2, (n + 63) / 64));
+            1, std::min<int64_t>((int64_t)di.cus * 8, (n * 16 + kBlock - 1) / kBlock));
         batch = launch && launch->pass_batch ? launch->pass_batch : std::min(max_pass, 8);
     }
 
@@ -1190,7 +1269,7 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
         for (int32_t b = 0; b < batch; ++b) {
             DSG_HIP(log.begin(kKindMark));
             k_mark_count<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, n);
-            k_scan_tiles<<<1, kBlock, 0, s>>>(w, 0, n);
+            k_scan_tiles<<<1, kScanBlock, 0, s>>>(w, 0, n);
             k_mark_scatter<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, n, walk_tiles(m),
                                                         nbins_cap);
             DSG_HIP(hipGetLastError());
@@ -1201,7 +1280,7 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
             DSG_HIP(log.end());
             DSG_HIP(log.begin(kKindApply));
             k_apply<<<apply_grid, kApplyBlock, 0, s>>>(w);
-            k_reduce<<<reduce_grid, kApplyBlock, 0, s>>>(w);
+            k_reduce<<<reduce_grid, kBlock, 0, s>>>(w);
             DSG_HIP(hipGetLastError());
             DSG_HIP(log.end());
             ++launched;
@@ -1209,7 +1288,7 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
         if (best_ids) {
             DSG_HIP(log.begin(kKindExtract));
             k_extract_count<<<mark_grid, kBlock, 0, s>>>(w, n);
-            k_scan_tiles<<<1, kBlock, 0, s>>>(w, 1, n);
+            k_scan_tiles<<<1, kScanBlock, 0, s>>>(w, 1, n);
             k_extract_scatter<<<mark_grid, kBlock, 0, s>>>(w, n, best_ids);
             DSG_HIP(hipGetLastError());
             DSG_HIP(log.end());
