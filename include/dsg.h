@@ -182,6 +182,133 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
  */
 int32_t dsg_validate_csr(const dsg_csr* g, int64_t n, int64_t m, int32_t* detail, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched peeling: many independent graphs in one persistent launch.
+ *
+ * Every graph of a batch is peeled exactly as dsg_peel peels it (same
+ * passes, same S~, same density); the batch only changes how the work is
+ * scheduled.  Graphs are stored back to back in three caller arrays:
+ *
+ *   row_ptr  device int32: graph g's n+1 row offsets start at
+ *            graphs[g].row_ptr_off and are local to the graph (its first
+ *            entry is 0, its last 2m).
+ *   col_idx  device int32: its 2m neighbour ids (local, 0..n-1) start at
+ *            graphs[g].col_idx_off.
+ *   best_ids / removed_at
+ *            device int32: graph g owns n slots from graphs[g].out_off; the
+ *            slot ranges of different graphs must not overlap.
+ *
+ * A persistent workgroup takes the next graph from a device queue ordered
+ * by decreasing size and runs all of that graph's passes: the mark, the
+ * neighbour walk and the degree update of Algorithm 1 (Section 3.1) with
+ * workgroup barriers in place of the paper's global barrier, and the degree
+ * and presence state of the graph's vertices held in LDS.
+ * ------------------------------------------------------------------------ */
+
+/* One graph of a batch (host struct). */
+typedef struct {
+    int64_t row_ptr_off; /* first of the graph's n+1 entries in row_ptr    */
+    int64_t col_idx_off; /* first of its 2m entries in col_idx              */
+    int64_t out_off;     /* first of its n slots in best_ids / removed_at   */
+    int64_t n;           /* vertices */
+    int64_t m;           /* undirected edges */
+    int64_t eps_num;     /* eps = eps_num / eps_den, per graph              */
+    int64_t eps_den;
+    int64_t reserved;    /* must be 0 */
+} dsg_batch_graph;
+
+/* Result of one graph of a batch (device struct, written by the kernel). */
+typedef struct {
+    int64_t dens_num;  /* |E(S~)| */
+    int64_t dens_den;  /* |S~| */
+    int32_t passes;
+    int32_t best_pass;
+    int64_t best_size; /* ids written to the graph's best_ids slots */
+    int32_t status;    /* DSG_OK; DSG_EINVAL when the device found the graph's
+                          row_ptr or col_idx outside the CSR contract;
+                          DSG_EINTERNAL when the pass watchdog or an
+                          edge-count invariant tripped */
+    int32_t reserved;
+} dsg_batch_result;
+
+/* Launch shape of the persistent kernel; 0 selects the library default.
+ * Results never depend on these. */
+typedef struct {
+    int32_t block;         /* threads per workgroup: 256, 512 or 1024        */
+    int32_t blocks_per_cu; /* workgroups resident per CU (LDS is split): 1..8 */
+    int32_t grid;          /* persistent workgroups (default CUs x blocks_per_cu) */
+    int32_t walk_items;    /* adjacency entries per lane per walk tile: 4, 8 or 16
+                              (16 only with 256 or 512 threads) */
+} dsg_batch_launch;
+
+/* A prepared batch (host struct, filled by dsg_batch_prepare and only read
+ * afterwards).  It refers to the workspace, which must stay allocated and
+ * unmodified while the plan is used. */
+typedef struct {
+    int32_t count;        /* graphs */
+    int32_t block;        /* chosen launch shape */
+    int32_t blocks_per_cu;
+    int32_t grid;
+    int32_t walk_items;
+    int32_t lds_bytes;    /* dynamic LDS per workgroup (vertex states) */
+    int32_t lds_vertices; /* vertices per graph whose state lives in LDS */
+    int32_t reserved0;
+    int64_t out_len;      /* slots of best_ids / removed_at */
+    void* workspace;
+    uint64_t ws_bytes;
+    int64_t reserved[4];
+} dsg_batch_plan;
+
+/* Device workspace bytes for a batch of `count` graphs whose adjacency
+ * arrays hold col_idx_len entries and whose output slots span out_len
+ * entries: 24 bytes per slot, 64 + 8 bytes per graph and 4 bytes per 256
+ * adjacency entries; 0 for invalid sizes. */
+size_t dsg_batch_workspace_bytes(int32_t count, int64_t col_idx_len, int64_t out_len);
+
+/*
+ * Check a batch on the host, order it for the device queue and upload its
+ * table into the workspace.  Synchronises `stream` once (the upload), makes
+ * no allocation, and fills *plan.
+ *
+ *   graphs       host, count entries (count >= 0).
+ *   row_ptr_len, col_idx_len, out_len
+ *                entries of the caller's row_ptr, col_idx and best_ids /
+ *                removed_at arrays; every graph's ranges must lie inside.
+ *   launch       host or NULL.
+ *   workspace    device, >= dsg_batch_workspace_bytes(count, col_idx_len,
+ *                out_len) bytes, 256-byte aligned.
+ *
+ * Errors: DSG_EINVAL for NULL pointers, count < 0, a short or misaligned
+ * workspace, a range outside its array, overlapping output ranges, a
+ * nonzero reserved field or an unsupported launch shape; DSG_EOVERFLOW
+ * when a graph fails the size limits of dsg_peel; DSG_EDEVICE for HIP
+ * failures.
+ */
+int32_t dsg_batch_prepare(const dsg_batch_graph* graphs, int32_t count, int64_t row_ptr_len,
+                          int64_t col_idx_len, int64_t out_len, const dsg_batch_launch* launch,
+                          void* workspace, size_t ws_bytes, void* stream, dsg_batch_plan* plan);
+
+/*
+ * Peel every graph of a prepared batch: two kernel launches on `stream`,
+ * no host synchronisation and no allocation, so the call can be captured
+ * into a HIP graph and replayed.  On completion results[i] (device, count
+ * entries, indexed like the caller's table) holds graph i's result and its
+ * best_ids slots hold S~ in ascending local ids.
+ *
+ *   row_ptr, col_idx  device batch arrays described to dsg_batch_prepare.
+ *   best_ids          device, out_len entries, or NULL to skip extraction.
+ *   removed_at        device, out_len entries, or NULL; receives the pass in
+ *                     which every vertex failed.
+ *
+ * Errors: DSG_EINVAL for a NULL plan or results or a plan that was not
+ * filled by dsg_batch_prepare; DSG_EDEVICE when a launch fails.  Per-graph
+ * problems are reported in results[i].status.  Calls sharing a workspace
+ * must be ordered (same stream).
+ */
+int32_t dsg_batch_run(const dsg_batch_plan* plan, const int32_t* row_ptr, const int32_t* col_idx,
+                      int32_t* best_ids, int32_t* removed_at, dsg_batch_result* results,
+                      void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,681 @@
+// batch.hip - many graphs peeled in one persistent launch (dsg_batch_* in
+// include/dsg.h).
+//
+// Each workgroup is a worker: it takes the next graph from a device queue
+// (graphs ordered by decreasing size, so the longest jobs start first) and
+// runs every pass of Algorithm 1 (P-Bahmani, Section 3.1) for that graph on
+// its own, with workgroup barriers where the paper has its global barrier.
+// Per pass:
+//
+//   mark    part 1 over the live list: failure test deg <= T_k, ordered
+//           compaction (workgroup prefix sums) of the survivors into the
+//           live list (in place) and of the failures with degree > 0 into
+//           the walk list, with the exclusive prefix of their row lengths
+//           and, for every wave tile of the flat walk range, the walk-list
+//           row that contains the tile's first entry.
+//   walk    part 2: every wave walks its own tiles of the flat range of the
+//           walk list's adjacency entries (hub rows split over tiles, no
+//           workgroup barrier) and decrements the degree of each neighbour
+//           still present; entries to vertices failing in the same pass
+//           are counted (intra), so |E| drops by cross + intra / 2.
+//   update  |V|, |E| and the best graph (strict improvement only).
+//
+// Vertex state lives in LDS as one 16-bit word per vertex for the first
+// `cap` vertex ids of the graph: the degree itself while below 0xFE00, an
+// index into a small LDS table of large degrees, or a marker for "failed in
+// this pass", "failed earlier" and "degree kept in device memory".  Degree
+// decrements are LDS atomics on the 32-bit word holding the 16-bit degree
+// (a degree is at least 1 before its decrement, so no borrow crosses the
+// half-word).  Vertex ids at or above `cap` (graphs larger than the LDS),
+// and large degrees beyond the table, use device memory and device atomics.
+//
+// All arithmetic is exact integer arithmetic, so results equal those of
+// dsg_peel and of a sequential peel for every launch shape.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "common.h"
+#include "dsg.h"
+#include "host.h"
+
+namespace dsg {
+namespace {
+
+// 16-bit vertex states
+constexpr uint32_t kStDead = 0xFFFFu;    // failed in an earlier pass
+constexpr uint32_t kStNow = 0xFFFEu;     // failed in the current pass
+constexpr uint32_t kStGlobal = 0xFFFDu;  // present, degree in device memory
+constexpr uint32_t kStSlot0 = 0xFE00u;   // present, degree in big-degree slot s - kStSlot0
+constexpr int kSlots = (int)(kStGlobal - kStSlot0);
+constexpr int kBMarkItems = 4;           // live-list entries per thread per mark chunk
+constexpr int kMinWaveTile = 64 * 4;     // smallest wave tile (sizes the tile table)
+constexpr uint64_t kPlanMagic = 0x44534742504c414eull;
+
+// One graph of the batch, in queue order (device copy).
+struct BGraph {
+    int64_t rp_off, ci_off, out_off, tf_off;
+    int64_t num, den;
+    int32_t n, m2, max_pass, index;
+};
+static_assert(sizeof(BGraph) == 64, "table row");
+
+struct alignas(256) BHead {
+    uint32_t next;  // queue cursor
+};
+
+struct BWork {
+    const BGraph* gs;
+    BHead* head;
+    int32_t* gdeg;  // degrees kept in device memory (ids >= cap, overflow)
+    int32_t* live;  // live list (compacted in place)
+    int32_t* alist; // walk list: failed vertex ids
+    int32_t* apre;  // walk list: exclusive prefix of row lengths
+    int32_t* abase; // walk list: row start - prefix (entry e of the flat range
+                    // of a row lies at col_idx[abase + e])
+    int32_t* rem;   // pass in which each vertex failed, kNever while present
+    int32_t* tf;    // per wave tile: walk-list row holding its first entry
+    int32_t* best;  // S~ output (may be null)
+    dsg_batch_result* res;
+    int32_t count;
+    int32_t cap;    // vertex ids with LDS state
+};
+
+static_assert(sizeof(dsg_batch_result) == 40, "result layout");
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int32_t load_coherent(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void dec_global(int32_t* p) {
+    __hip_atomic_fetch_sub(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Degree of a vertex still present.
+__device__ inline int32_t live_degree(int32_t v, int32_t cap, const uint16_t* st16,
+                                      const int32_t* big, const int32_t* gdeg) {
+    if (v < cap) {
+        const uint32_t s = st16[v];
+        if (s < kStSlot0) return (int32_t)s;
+        if (s < kStGlobal) return big[s - kStSlot0];
+    }
+    return load_coherent(gdeg + v);
+}
+
+template <int NT, int IT>
+__global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __restrict__ rp_all,
+                                                   const int32_t* __restrict__ ci_all) {
+    constexpr int NW = NT / 64;
+    constexpr int WT = 64 * IT;          // wave tile
+    constexpr int CH = NT * kBMarkItems;  // mark chunk
+    static_assert(IT % 4 == 0, "owner rows move as int4");
+    extern __shared__ uint32_t s_state[];  // two 16-bit vertex states per word
+    __shared__ __align__(16) int32_t s_own[NW * WT];
+    __shared__ int32_t s_big[kSlots];
+    __shared__ unsigned long long s_red64[NW];
+    __shared__ uint32_t s_red32[NW];
+    __shared__ int32_t s_q, s_nslots;
+
+    uint16_t* st16 = reinterpret_cast<uint16_t*>(s_state);
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wid = wave_id();
+    int32_t* own = s_own + wid * WT;
+
+    for (;;) {
+        if (tid == 0) s_q = (int32_t)atomicAdd(&w.head->next, 1u);
+        __syncthreads();
+        const int32_t q = s_q;
+        __syncthreads();
+        if (q >= w.count) break;
+
+        const BGraph g = w.gs[q];
+        const int32_t n = g.n;
+        const int32_t m2 = g.m2;
+        const int32_t* __restrict__ rp = rp_all + g.rp_off;
+        const int32_t* __restrict__ ci = ci_all + g.ci_off;
+        int32_t* __restrict__ rem = w.rem + g.out_off;
+        int32_t* __restrict__ gdeg = w.gdeg + g.out_off;
+        int32_t* __restrict__ live = w.live + g.out_off;
+        int32_t* __restrict__ alist = w.alist + g.out_off;
+        int32_t* __restrict__ apre = w.apre + g.out_off;
+        int32_t* __restrict__ abase = w.abase + g.out_off;
+        int32_t* __restrict__ tf = w.tf + g.tf_off;
+        const int32_t cap = min(n, w.cap);
+
+        int64_t S = n, E = m2 / 2, bE = E, bS = S;
+        int32_t pass = 0, bp = 0, status = DSG_OK, found = 0;
+
+        // the row offsets must run from 0 to 2m without decreasing
+        if (n > 0) {
+            int32_t bad = (rp[0] != 0 || rp[n] != m2) ? 1 : 0;
+            for (int32_t v = tid; v < n && !bad; v += NT) bad = rp[v] > rp[v + 1];
+            if (tid == 0) s_nslots = 0;
+            if (__syncthreads_or(bad)) status = DSG_EINVAL;
+        }
+
+        while (status == DSG_OK && S > 0) {
+            ++pass;
+            if (pass > g.max_pass) {
+                status = DSG_EINTERNAL;
+                break;
+            }
+            const int32_t T = pass_threshold(E, S, g.num, g.den);
+            const int32_t nlive = (int32_t)S;
+
+            // ------------------------------------------------ mark
+            int32_t nA = 0, nL = 0, W = 0;
+            for (int32_t base = 0; base < nlive; base += CH) {
+                int32_t v[kBMarkItems], d[kBMarkItems], rs[kBMarkItems], rl[kBMarkItems];
+                const int32_t i0 = base + tid * kBMarkItems;
+#pragma unroll
+                for (int j = 0; j < kBMarkItems; ++j) {
+                    const int32_t i = i0 + j;
+                    v[j] = -1;
+                    d[j] = 0;
+                    rs[j] = 0;
+                    rl[j] = 0;
+                    if (i < nlive) {
+                        if (pass == 1) {
+                            v[j] = i;
+                            rs[j] = rp[i];
+                            rl[j] = rp[i + 1] - rs[j];
+                            d[j] = rl[j];
+                        } else {
+                            v[j] = live[i];
+                        }
+                    }
+                }
+                if (pass > 1) {
+#pragma unroll
+                    for (int j = 0; j < kBMarkItems; ++j)
+                        if (v[j] >= 0) d[j] = live_degree(v[j], cap, st16, s_big, gdeg);
+#pragma unroll
+                    for (int j = 0; j < kBMarkItems; ++j)
+                        if (v[j] >= 0 && d[j] > 0 && d[j] <= T) {
+                            rs[j] = rp[v[j]];
+                            rl[j] = rp[v[j] + 1] - rs[j];
+                        }
+                }
+                uint32_t cA = 0, cL = 0, sl = 0;
+#pragma unroll
+                for (int j = 0; j < kBMarkItems; ++j) {
+                    if (v[j] < 0) continue;
+                    if (d[j] > T) {
+                        ++cL;
+                    } else if (d[j] > 0) {
+                        ++cA;
+                        sl += (uint32_t)rl[j];
+                    }
+                }
+                // one scan for the three counts: row-length sum (< 2^31 for a
+                // valid CSR) in the low word, walk-list and live-list counts
+                // (<= CH < 2^16) in the two high half-words
+                const unsigned long long mine = (unsigned long long)sl |
+                                                ((unsigned long long)cA << 32) |
+                                                ((unsigned long long)cL << 48);
+                unsigned long long tot;
+                const unsigned long long ex =
+                    block_excl_sum<unsigned long long, NW>(mine, s_red64, &tot);
+                int32_t oa = nA + (int32_t)((ex >> 32) & 0xFFFFu);
+                int32_t ol = nL + (int32_t)(ex >> 48);
+                int32_t wo = W + (int32_t)(uint32_t)ex;
+#pragma unroll
+                for (int j = 0; j < kBMarkItems; ++j) {
+                    const int32_t x = v[j];
+                    if (x < 0) continue;
+                    if (d[j] > T) {
+                        live[ol++] = x;
+                        if (pass == 1) {
+                            rem[x] = kNever;
+                            const int32_t dx = d[j];
+                            bool in_lds = false;
+                            if (x < cap) {
+                                if (dx < (int32_t)kStSlot0) {
+                                    st16[x] = (uint16_t)dx;
+                                    in_lds = true;
+                                } else {
+                                    const int32_t s = atomicAdd(&s_nslots, 1);
+                                    if (s < kSlots) {
+                                        s_big[s] = dx;
+                                        st16[x] = (uint16_t)(kStSlot0 + s);
+                                        in_lds = true;
+                                    } else {
+                                        st16[x] = (uint16_t)kStGlobal;
+                                    }
+                                }
+                            }
+                            if (!in_lds) gdeg[x] = dx;
+                        }
+                    } else {
+                        rem[x] = pass;
+                        if (x < cap) st16[x] = (uint16_t)(d[j] > 0 ? kStNow : kStDead);
+                        if (d[j] > 0) {
+                            alist[oa] = x;
+                            apre[oa] = wo;
+                            abase[oa] = rs[j] - wo;
+                            // wave tiles whose first entry lies in this row
+                            const int32_t end = wo + rl[j];
+                            for (int32_t t = (wo + WT - 1) / WT; t * WT < end; ++t) tf[t] = oa;
+                            ++oa;
+                            wo = end;
+                        }
+                    }
+                }
+                nA += (int32_t)((tot >> 32) & 0xFFFFu);
+                nL += (int32_t)(tot >> 48);
+                W += (int32_t)(uint32_t)tot;
+            }
+            __threadfence();
+            __syncthreads();
+
+            // ------------------------------------------------ walk
+            uint32_t cross = 0, intra = 0, badc = 0;
+            if (nL > 0 && W > 0) {
+                const int32_t ntile = (W + WT - 1) / WT;
+                for (int k = lane; k < WT; k += 64) own[k] = 0;
+                for (int32_t t = wid; t < ntile; t += NW) {
+                    const int32_t t0 = t * WT;
+                    const int32_t len = min(WT, W - t0);
+                    const int32_t rc = tf[t];
+                    // rows that start inside the tile: mark their first entry
+                    for (int32_t r = rc + 1 + lane; r < nA; r += 64) {
+                        const int32_t s = apre[r];
+                        if (s >= t0 + len) break;
+                        own[s - t0] = r;
+                    }
+                    wave_sync();
+                    // owner of every entry: running max over the marks (rows
+                    // start at increasing offsets; older marks are <= rc)
+                    int32_t row[IT];
+                    int32_t run = rc;
+                    {
+                        const int4* o4 = reinterpret_cast<const int4*>(own + lane * IT);
+#pragma unroll
+                        for (int k = 0; k < IT / 4; ++k) {
+                            const int4 x = o4[k];
+                            row[4 * k + 0] = run = max(run, x.x);
+                            row[4 * k + 1] = run = max(run, x.y);
+                            row[4 * k + 2] = run = max(run, x.z);
+                            row[4 * k + 3] = run = max(run, x.w);
+                        }
+                    }
+                    const int32_t inc = wave_incl_max(run);
+                    int32_t carry = __shfl_up(inc, 1, 64);
+                    if (lane == 0) carry = rc;
+                    wave_sync();
+                    {
+                        int4* o4 = reinterpret_cast<int4*>(own + lane * IT);
+#pragma unroll
+                        for (int k = 0; k < IT / 4; ++k)
+                            o4[k] = make_int4(max(row[4 * k + 0], carry), max(row[4 * k + 1], carry),
+                                              max(row[4 * k + 2], carry), max(row[4 * k + 3], carry));
+                    }
+                    wave_sync();
+                    // neighbour ids, consecutive lanes on consecutive entries
+                    int32_t u[IT];
+#pragma unroll
+                    for (int j = 0; j < IT; ++j) {
+                        const int p = j * 64 + lane;
+                        u[j] = -1;
+                        if (p < len) {
+                            const int32_t pos = abase[own[p]] + t0 + p;
+                            u[j] = __builtin_nontemporal_load(ci + pos);
+                        }
+                    }
+                    wave_sync();
+#pragma unroll
+                    for (int j = 0; j < IT; ++j) {
+                        const int p = j * 64 + lane;
+                        if (p >= len) continue;
+                        const int32_t x = u[j];
+                        if ((uint32_t)x >= (uint32_t)n) {
+                            ++badc;
+                        } else if (x < cap) {
+                            const uint32_t s = st16[x];
+                            if (s < kStSlot0) {
+                                atomicSub(&s_state[x >> 1], 1u << ((x & 1) << 4));
+                                ++cross;
+                            } else if (s < kStGlobal) {
+                                atomicSub(&s_big[s - kStSlot0], 1);
+                                ++cross;
+                            } else if (s == kStGlobal) {
+                                dec_global(gdeg + x);
+                                ++cross;
+                            } else if (s == kStNow) {
+                                ++intra;
+                            }
+                        } else {
+                            const int32_t r = rem[x];
+                            if (r == kNever) {
+                                dec_global(gdeg + x);
+                                ++cross;
+                            } else if (r == pass) {
+                                ++intra;
+                            }
+                        }
+                    }
+                }
+            }
+            __threadfence();
+            const unsigned long long ci_sum = block_sum<unsigned long long, NW>(
+                (unsigned long long)cross | ((unsigned long long)intra << 32), s_red64);
+            const uint32_t bad_sum = block_sum<uint32_t, NW>(badc, s_red32);
+
+            // ------------------------------------------------ update
+            const int64_t cr = (int64_t)(ci_sum & 0xFFFFFFFFull);
+            const int64_t in = (int64_t)(ci_sum >> 32);
+            if (bad_sum) {
+                status = DSG_EINVAL;
+                break;
+            }
+            const int64_t Eo = nL > 0 ? E - cr - in / 2 : 0;
+            if ((nL > 0 && (in & 1)) || Eo < 0) {
+                status = DSG_EINTERNAL;
+                break;
+            }
+            S = nL;
+            E = Eo;
+            if (S > 0 && E * bS > bE * S) {
+                bE = E;
+                bS = S;
+                bp = pass;
+            }
+            // this pass's failures are gone from the next pass on
+            for (int32_t r = tid; r < nA; r += NT) {
+                const int32_t x = alist[r];
+                if (x < cap) st16[x] = (uint16_t)kStDead;
+            }
+        }
+
+        // ---------------------------------------------------- extract
+        if (status == DSG_OK && w.best && n > 0) {
+            int32_t* __restrict__ out = w.best + g.out_off;
+            for (int32_t base = 0; base < n; base += CH) {
+                const int32_t i0 = base + tid * kBMarkItems;
+                uint32_t keep = 0, c = 0;
+#pragma unroll
+                for (int j = 0; j < kBMarkItems; ++j) {
+                    const int32_t i = i0 + j;
+                    if (i < n && rem[i] > bp) {
+                        keep |= 1u << j;
+                        ++c;
+                    }
+                }
+                uint32_t tot;
+                uint32_t at = block_excl_sum<uint32_t, NW>(c, s_red32, &tot);
+                at += (uint32_t)found;
+#pragma unroll
+                for (int j = 0; j < kBMarkItems; ++j)
+                    if (keep >> j & 1u) out[at++] = i0 + j;
+                found += (int32_t)tot;
+            }
+            if (found != bS) status = DSG_EINTERNAL;
+        }
+        if (tid == 0) {
+            dsg_batch_result r;
+            r.dens_num = n > 0 ? bE : 0;
+            r.dens_den = n > 0 ? bS : 0;
+            r.passes = pass;
+            r.best_pass = bp;
+            r.best_size = found;
+            r.status = status;
+            r.reserved = 0;
+            w.res[g.index] = r;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_batch_reset(BHead* head) {
+    if (threadIdx.x == 0) head->next = 0;
+}
+
+// ------------------------------------------------------------------ host
+
+using BatchFn = void (*)(BWork, const int32_t*, const int32_t*);
+
+template <int NT, int IT>
+hipError_t launch_one(const dsg_batch_plan* p, const BWork& w, const int32_t* rp,
+                      const int32_t* ci, hipStream_t s) {
+    hipLaunchKernelGGL((k_batch_peel<NT, IT>), dim3(p->grid), dim3(NT), (size_t)p->lds_bytes, s,
+                       w, rp, ci);
+    return hipGetLastError();
+}
+
+template <int NT, int IT>
+const void* kernel_ptr() {
+    return reinterpret_cast<const void*>(&k_batch_peel<NT, IT>);
+}
+
+// Supported (block, walk_items) shapes (1024 x 16 would spill registers).
+const void* batch_kernel(int block, int items) {
+#define DSG_SHAPE(NT, IT) \
+    if (block == NT && items == IT) return kernel_ptr<NT, IT>();
+    DSG_SHAPE(256, 4) DSG_SHAPE(256, 8) DSG_SHAPE(256, 16)
+    DSG_SHAPE(512, 4) DSG_SHAPE(512, 8) DSG_SHAPE(512, 16)
+    DSG_SHAPE(1024, 4) DSG_SHAPE(1024, 8)
+#undef DSG_SHAPE
+    return nullptr;
+}
+
+hipError_t batch_launch(const dsg_batch_plan* p, const BWork& w, const int32_t* rp,
+                        const int32_t* ci, hipStream_t s) {
+#define DSG_SHAPE(NT, IT) \
+    if (p->block == NT && p->walk_items == IT) return launch_one<NT, IT>(p, w, rp, ci, s);
+    DSG_SHAPE(256, 4) DSG_SHAPE(256, 8) DSG_SHAPE(256, 16)
+    DSG_SHAPE(512, 4) DSG_SHAPE(512, 8) DSG_SHAPE(512, 16)
+    DSG_SHAPE(1024, 4) DSG_SHAPE(1024, 8)
+#undef DSG_SHAPE
+    return hipErrorInvalidValue;
+}
+
+struct BLayout {
+    size_t head, table, tf, gdeg, live, alist, apre, abase, rem, total;
+};
+
+BLayout batch_layout(int64_t count, int64_t ci_len, int64_t out_len) {
+    BLayout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.head = take(sizeof(BHead));
+    L.table = take(sizeof(BGraph) * (size_t)count);
+    L.tf = take(4 * (size_t)(ci_len / kMinWaveTile + 2 * count + 1));
+    L.gdeg = take(4 * (size_t)out_len);
+    L.live = take(4 * (size_t)out_len);
+    L.alist = take(4 * (size_t)out_len);
+    L.apre = take(4 * (size_t)out_len);
+    L.abase = take(4 * (size_t)out_len);
+    L.rem = take(4 * (size_t)out_len);
+    L.total = o;
+    return L;
+}
+
+struct BDevInfo {
+    int cus = 0;
+    int lds_per_cu = 0;
+    int lds_per_block = 0;
+    bool ready = false;
+};
+std::mutex g_bmu;
+BDevInfo g_binfo[64];
+
+hipError_t batch_device_info(BDevInfo* out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_bmu);
+    BDevInfo& d = g_binfo[dev];
+    if (!d.ready) {
+        e = hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&d.lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                  dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&d.lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e != hipSuccess) return e;
+        if (d.lds_per_cu <= 0) d.lds_per_cu = d.lds_per_block;
+        d.ready = true;
+    }
+    *out = d;
+    return hipSuccess;
+}
+
+}  // namespace
+}  // namespace dsg
+
+using namespace dsg;
+
+extern "C" {
+
+size_t dsg_batch_workspace_bytes(int32_t count, int64_t col_idx_len, int64_t out_len) {
+    if (count < 0 || col_idx_len < 0 || out_len < 0) return 0;
+    if (out_len > ((int64_t)1 << 40) || col_idx_len > ((int64_t)1 << 42)) return 0;
+    return batch_layout(count, col_idx_len, out_len).total;
+}
+
+int32_t dsg_batch_prepare(const dsg_batch_graph* graphs, int32_t count, int64_t row_ptr_len,
+                          int64_t col_idx_len, int64_t out_len, const dsg_batch_launch* launch,
+                          void* workspace, size_t ws_bytes, void* stream, dsg_batch_plan* plan) {
+    if (!plan || count < 0 || (count > 0 && !graphs)) return DSG_EINVAL;
+    if (row_ptr_len < 0 || col_idx_len < 0 || out_len < 0) return DSG_EINVAL;
+    const size_t need = dsg_batch_workspace_bytes(count, col_idx_len, out_len);
+    if (need == 0 || !workspace || ws_bytes < need || ((uintptr_t)workspace & 255u))
+        return DSG_EINVAL;
+
+    int32_t block = 1024, bpc = 1, items = 8, grid = 0;
+    if (launch) {
+        if (launch->block) block = launch->block;
+        if (launch->blocks_per_cu) bpc = launch->blocks_per_cu;
+        if (launch->walk_items) items = launch->walk_items;
+        grid = launch->grid;
+    }
+    if (bpc < 1 || bpc > 8 || grid < 0 || !batch_kernel(block, items)) return DSG_EINVAL;
+
+    // per-graph checks, the device table and the queue order
+    std::vector<BGraph> tab((size_t)count);
+    std::vector<std::pair<int64_t, int64_t>> outs;
+    outs.reserve((size_t)count);
+    int64_t tf_at = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const dsg_batch_graph& g = graphs[i];
+        if (g.reserved != 0) return DSG_EINVAL;
+        const int32_t rc = check_sizes(g.n, g.m, g.eps_num, g.eps_den);
+        if (rc != DSG_OK) return rc;
+        if (g.row_ptr_off < 0 || g.col_idx_off < 0 || g.out_off < 0) return DSG_EINVAL;
+        // an empty graph reads no row offsets
+        if (g.row_ptr_off > row_ptr_len || (g.n > 0 && g.row_ptr_off > row_ptr_len - (g.n + 1)))
+            return DSG_EINVAL;
+        if (g.col_idx_off > col_idx_len - 2 * g.m) return DSG_EINVAL;
+        if (g.out_off > out_len - g.n) return DSG_EINVAL;
+        if (g.n > 0) outs.emplace_back(g.out_off, g.n);
+        BGraph& b = tab[(size_t)i];
+        b.rp_off = g.row_ptr_off;
+        b.ci_off = g.col_idx_off;
+        b.out_off = g.out_off;
+        b.tf_off = tf_at;
+        tf_at += 2 * g.m / kMinWaveTile + 2;
+        b.num = g.eps_num;
+        b.den = g.eps_den;
+        b.n = (int32_t)g.n;
+        b.m2 = (int32_t)(2 * g.m);
+        b.max_pass = pass_bound(g.n, g.eps_num, g.eps_den);
+        b.index = i;
+    }
+    std::sort(outs.begin(), outs.end());
+    for (size_t i = 1; i < outs.size(); ++i)
+        if (outs[i - 1].first + outs[i - 1].second > outs[i].first) return DSG_EINVAL;
+    // largest graphs first: adjacency entries, then vertices, then table order
+    std::stable_sort(tab.begin(), tab.end(), [](const BGraph& a, const BGraph& b) {
+        const int64_t wa = (int64_t)a.m2 + a.n, wb = (int64_t)b.m2 + b.n;
+        return wa > wb;
+    });
+
+    BDevInfo di;
+    hipError_t e = batch_device_info(&di);
+    if (e != hipSuccess) return map_hip(e);
+    const void* fn = batch_kernel(block, items);
+    hipFuncAttributes attr;
+    e = hipFuncGetAttributes(&attr, fn);
+    if (e != hipSuccess) return map_hip(e);
+    const int64_t budget = std::min<int64_t>(di.lds_per_block, di.lds_per_cu / bpc);
+    const int64_t dyn = ((budget - (int64_t)attr.sharedSizeBytes) / 4) * 4;
+    if (dyn < 4) return DSG_EINVAL;
+    // allow the largest request any plan of this kernel can make
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(di.lds_per_block - (int64_t)attr.sharedSizeBytes));
+    if (e != hipSuccess) return map_hip(e);
+
+    const BLayout L = batch_layout(count, col_idx_len, out_len);
+    char* base = static_cast<char*>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (count > 0) {
+        e = hipMemcpyAsync(base + L.table, tab.data(), sizeof(BGraph) * tab.size(),
+                           hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return map_hip(e);
+    }
+
+    std::memset(plan, 0, sizeof(*plan));
+    plan->count = count;
+    plan->block = block;
+    plan->blocks_per_cu = bpc;
+    plan->walk_items = items;
+    const int64_t g_def = (int64_t)di.cus * bpc;
+    plan->grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(grid ? grid : g_def, count));
+    plan->lds_bytes = (int32_t)dyn;
+    plan->lds_vertices = (int32_t)std::min<int64_t>(2 * (dyn / 4), INT32_MAX);
+    plan->out_len = out_len;
+    plan->workspace = workspace;
+    plan->ws_bytes = need;
+    plan->reserved[0] = (int64_t)kPlanMagic;
+    plan->reserved[1] = col_idx_len;
+    return DSG_OK;
+}
+
+int32_t dsg_batch_run(const dsg_batch_plan* plan, const int32_t* row_ptr, const int32_t* col_idx,
+                      int32_t* best_ids, int32_t* removed_at, dsg_batch_result* results,
+                      void* stream) {
+    if (!plan || plan->reserved[0] != (int64_t)kPlanMagic || !plan->workspace) return DSG_EINVAL;
+    if (plan->count == 0) return DSG_OK;
+    if (!results || !row_ptr || !col_idx) return DSG_EINVAL;
+    const BLayout L = batch_layout(plan->count, plan->reserved[1], plan->out_len);
+    char* base = static_cast<char*>(plan->workspace);
+    BWork w;
+    w.gs = reinterpret_cast<const BGraph*>(base + L.table);
+    w.head = reinterpret_cast<BHead*>(base + L.head);
+    w.gdeg = reinterpret_cast<int32_t*>(base + L.gdeg);
+    w.live = reinterpret_cast<int32_t*>(base + L.live);
+    w.alist = reinterpret_cast<int32_t*>(base + L.alist);
+    w.apre = reinterpret_cast<int32_t*>(base + L.apre);
+    w.abase = reinterpret_cast<int32_t*>(base + L.abase);
+    w.rem = removed_at ? removed_at : reinterpret_cast<int32_t*>(base + L.rem);
+    w.tf = reinterpret_cast<int32_t*>(base + L.tf);
+    w.best = best_ids;
+    w.res = results;
+    w.count = plan->count;
+    w.cap = plan->lds_vertices;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    k_batch_reset<<<1, 64, 0, s>>>(w.head);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = batch_launch(plan, w, row_ptr, col_idx, s);
+    return e == hipSuccess ? DSG_OK : map_hip(e);
+}
+
+}  // extern "C"

@@ -59,6 +59,7 @@
 
 #include "common.h"
 #include "dsg.h"
+#include "host.h"
 
 namespace dsg {
 
@@ -1021,8 +1022,6 @@ hipError_t device_info(DevInfo* out) {
     return hipSuccess;
 }
 
-inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
-
 inline int64_t mark_tiles(int64_t n) { return (n + kMarkTile - 1) / kMarkTile + 1; }
 inline int64_t walk_tiles(int64_t m) { return (2 * m + kWalkTile - 1) / kWalkTile + 1; }
 inline int64_t max_bins(int64_t n) { return (n + kBinWidth - 1) / kBinWidth + 1; }
@@ -1081,31 +1080,6 @@ Layout layout(int64_t n, int64_t m) {
     return L;
 }
 
-int32_t check_sizes(int64_t n, int64_t m, int64_t num, int64_t den) {
-    if (n < 0 || m < 0 || den < 1 || num < 0) return DSG_EINVAL;
-    if (n > (int64_t)INT32_MAX - 1) return DSG_EOVERFLOW;
-    if (2 * (__int128)m > (__int128)INT32_MAX) return DSG_EOVERFLOW;
-    if (num > INT64_MAX - den) return DSG_EOVERFLOW;
-    const __int128 lim = (__int128)1 << 63;
-    if ((__int128)2 * ((__int128)num + den) * m >= lim) return DSG_EOVERFLOW;
-    if ((__int128)n * den >= lim) return DSG_EOVERFLOW;
-    return DSG_OK;
-}
-
-// Upper bound on the number of passes: every pass of a valid input leaves
-// fewer than |V| / (1 + eps) vertices, so log_{1+eps} n passes plus a margin
-// suffice; with eps = 0 every pass still removes a vertex, so n passes do.
-int32_t pass_bound(int64_t n, int64_t num, int64_t den) {
-    if (n <= 1) return (int32_t)n;
-    if (num == 0) return (int32_t)n;
-    const double k = std::ceil(std::log((double)n) / std::log1p((double)num / (double)den));
-    const double b = std::min((double)n, k + 2.0);
-    return (int32_t)std::max(1.0, b);
-}
-
-int32_t map_hip(hipError_t e) {
-    return e == hipErrorOutOfMemory ? DSG_ENOMEM : DSG_EDEVICE;
-}
 
 thread_local DevState* t_host_state = nullptr;
 

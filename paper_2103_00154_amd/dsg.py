@@ -26,7 +26,8 @@ DSG_EINTERNAL = -5
 
 #: every symbol include/dsg.h declares
 EXPORTS = ("dsg_version", "dsg_strerror", "dsg_workspace_bytes", "dsg_peel", "dsg_peel_ex",
-           "dsg_validate_csr")
+           "dsg_validate_csr", "dsg_batch_workspace_bytes", "dsg_batch_prepare",
+           "dsg_batch_run")
 
 TRACE_FIELDS = ("s_in", "e_in", "thresh", "removed", "cross", "intra", "walked", "s_out", "e_out")
 
@@ -60,6 +61,27 @@ class Profile(ctypes.Structure):
                 ("launches_walk", _I32), ("launches_mark", _I32), ("launches_apply", _I32),
                 ("reserved", _I32), ("walked", _I64), ("cross", _I64),
                 ("live_scanned", _I64), ("walk_list", _I64)]
+
+
+class BatchGraph(ctypes.Structure):
+    _fields_ = [("row_ptr_off", _I64), ("col_idx_off", _I64), ("out_off", _I64), ("n", _I64),
+                ("m", _I64), ("eps_num", _I64), ("eps_den", _I64), ("reserved", _I64)]
+
+
+class BatchResult(ctypes.Structure):
+    _fields_ = [("dens_num", _I64), ("dens_den", _I64), ("passes", _I32), ("best_pass", _I32),
+                ("best_size", _I64), ("status", _I32), ("reserved", _I32)]
+
+
+class BatchLaunch(ctypes.Structure):
+    _fields_ = [("block", _I32), ("blocks_per_cu", _I32), ("grid", _I32), ("walk_items", _I32)]
+
+
+class BatchPlan(ctypes.Structure):
+    _fields_ = [("count", _I32), ("block", _I32), ("blocks_per_cu", _I32), ("grid", _I32),
+                ("walk_items", _I32), ("lds_bytes", _I32), ("lds_vertices", _I32),
+                ("reserved0", _I32), ("out_len", _I64), ("workspace", _P),
+                ("ws_bytes", ctypes.c_uint64), ("reserved", _I64 * 4)]
 
 
 class DsgError(RuntimeError):
@@ -99,6 +121,13 @@ def lib():
         h.dsg_peel_ex.restype = _I32
         h.dsg_validate_csr.argtypes = [ctypes.POINTER(CSR), _I64, _I64, ctypes.POINTER(_I32), _P]
         h.dsg_validate_csr.restype = _I32
+        h.dsg_batch_workspace_bytes.argtypes = [_I32, _I64, _I64]
+        h.dsg_batch_workspace_bytes.restype = _SZ
+        h.dsg_batch_prepare.argtypes = [_P, _I32, _I64, _I64, _I64, _P, _P, _SZ, _P,
+                                        ctypes.POINTER(BatchPlan)]
+        h.dsg_batch_prepare.restype = _I32
+        h.dsg_batch_run.argtypes = [ctypes.POINTER(BatchPlan), _P, _P, _P, _P, _P, _P]
+        h.dsg_batch_run.restype = _I32
         _lib = h
     return _lib
 
@@ -241,3 +270,107 @@ def validate_csr(row_ptr, col_idx, m: int | None = None, stream=None) -> int:
     if rc != DSG_OK:
         raise DsgError(rc, "dsg_validate_csr")
     return 0
+
+
+# --------------------------------------------------------------------------
+# batches: many graphs in one persistent launch
+# --------------------------------------------------------------------------
+
+#: int64 words per dsg_batch_result
+RESULT_WORDS = ctypes.sizeof(BatchResult) // 8
+
+
+def batch_workspace_bytes(count: int, col_idx_len: int, out_len: int) -> int:
+    return int(lib().dsg_batch_workspace_bytes(count, col_idx_len, out_len))
+
+
+def batch_table(n, m, row_ptr_off, col_idx_off, out_off, eps):
+    """ctypes array of dsg_batch_graph rows from per-graph sequences; ``eps``
+    is one (num, den) pair for all graphs or a sequence of pairs."""
+    count = len(n)
+    tab = (BatchGraph * max(count, 1))()
+    per_graph = count > 0 and isinstance(eps[0], (tuple, list))
+    for i in range(count):
+        num, den = eps[i] if per_graph else eps
+        tab[i] = BatchGraph(int(row_ptr_off[i]), int(col_idx_off[i]), int(out_off[i]), int(n[i]),
+                            int(m[i]), int(num), int(den), 0)
+    return tab, count
+
+
+class Batch:
+    """A prepared batch: the table uploaded into a device workspace and the
+    launch shape chosen (dsg_batch_prepare).  :meth:`run` enqueues the
+    persistent launch and returns at once; :meth:`results` reads them."""
+
+    def __init__(self, table, count: int, row_ptr_len: int, col_idx_len: int, out_len: int, *,
+                 launch: dict | None = None, workspace=None, device=None, stream=None):
+        import torch
+        self.count = count
+        self.out_len = out_len
+        dev = torch.device(device or "cuda")
+        nbytes = batch_workspace_bytes(count, col_idx_len, out_len)
+        if nbytes == 0:
+            raise DsgError(DSG_EINVAL, "dsg_batch_workspace_bytes")
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.workspace = workspace
+        ln = None
+        if launch:
+            ln = BatchLaunch(int(launch.get("block", 0)), int(launch.get("blocks_per_cu", 0)),
+                             int(launch.get("grid", 0)), int(launch.get("walk_items", 0)))
+        self.plan = BatchPlan()
+        with torch.cuda.device(dev):
+            rc = lib().dsg_batch_prepare(ctypes.addressof(table), count, row_ptr_len, col_idx_len,
+                                         out_len, ctypes.byref(ln) if ln is not None else None,
+                                         workspace.data_ptr(),
+                                         workspace.numel() * workspace.element_size(),
+                                         _stream_handle(stream), ctypes.byref(self.plan))
+        if rc != DSG_OK:
+            raise DsgError(rc, "dsg_batch_prepare")
+        self.device = dev
+
+    @property
+    def shape(self) -> dict:
+        p = self.plan
+        return {"block": p.block, "blocks_per_cu": p.blocks_per_cu, "grid": p.grid,
+                "walk_items": p.walk_items, "lds_bytes": p.lds_bytes,
+                "lds_vertices": p.lds_vertices}
+
+    def run(self, row_ptr, col_idx, *, best_ids=None, removed_at=None, results=None,
+            stream=None):
+        """Enqueue the peel of every graph; returns the device result tensor
+        (int64, count x RESULT_WORDS).  No host synchronisation."""
+        import torch
+        _check_int32_cuda("row_ptr", row_ptr)
+        _check_int32_cuda("col_idx", col_idx)
+        for name, t in (("best_ids", best_ids), ("removed_at", removed_at)):
+            if t is not None:
+                _check_int32_cuda(name, t)
+                if t.numel() < self.out_len:
+                    raise ValueError(f"{name} needs {self.out_len} entries")
+        if results is None:
+            results = torch.empty((max(self.count, 1), RESULT_WORDS), dtype=torch.int64,
+                                  device=self.device)
+        with torch.cuda.device(self.device):
+            rc = lib().dsg_batch_run(ctypes.byref(self.plan), row_ptr.data_ptr(),
+                                     col_idx.data_ptr(),
+                                     best_ids.data_ptr() if best_ids is not None else None,
+                                     removed_at.data_ptr() if removed_at is not None else None,
+                                     results.data_ptr(), _stream_handle(stream))
+        if rc != DSG_OK:
+            raise DsgError(rc, "dsg_batch_run")
+        return results
+
+    @staticmethod
+    def results(res) -> list[dict]:
+        """Host list of per-graph result dicts from a device result tensor."""
+        import numpy as np
+        a = res.cpu().numpy().astype(np.int64)
+        out = []
+        for row in a:
+            out.append({"num": int(row[0]), "den": int(row[1]),
+                        "passes": int(np.int32(row[2] & 0xFFFFFFFF)),
+                        "best_pass": int(np.int32((row[2] >> 32) & 0xFFFFFFFF)),
+                        "best_size": int(row[3]),
+                        "status": int(np.int32(row[4] & 0xFFFFFFFF))})
+        return out

@@ -46,6 +46,12 @@ def _gen():
         lib.gg_keys_to_csr.restype = _I32
         lib.gg_draw_for_test.argtypes = [_U64, _U64, _U64]
         lib.gg_draw_for_test.restype = _U64
+        lib.gg_batch_generate.argtypes = [_I32, _P, _P, _P, _P, _P, _P]
+        lib.gg_batch_generate.restype = _P
+        lib.gg_batch_copy.argtypes = [_P, _P, _P, _P, _P]
+        lib.gg_batch_copy.restype = _I32
+        lib.gg_batch_free.argtypes = [_P]
+        lib.gg_batch_free.restype = None
         _lib = lib
     return _lib
 
@@ -236,3 +242,131 @@ def random_small(n: int, p: float, seed: int) -> Graph:
 
 def draw_for_test(seed: int, stream: int, i: int) -> int:
     return int(_gen().gg_draw_for_test(seed, stream, i))
+
+
+# --------------------------------------------------------------------------
+# batches of independent graphs, stored back to back
+# --------------------------------------------------------------------------
+
+KIND_ER = 0
+KIND_CHUNG_LU = 1
+
+
+@dataclass
+class GraphSpec:
+    """Recipe of one batch graph: G(n, size) for kind 0, Chung-Lu with
+    ``size`` endpoint pairs and exponent ``gamma`` for kind 1."""
+
+    kind: int
+    n: int
+    size: int
+    gamma: float
+    seed: int
+    avg_deg: float
+
+
+@dataclass
+class Batch:
+    """Graphs stored back to back: graph i has n[i] vertices and m[i] edges,
+    its local row offsets at row_ptr[rp_off[i] : rp_off[i] + n[i] + 1], its
+    neighbour ids at col_idx[ci_off[i] : ci_off[i] + 2 m[i]], and owns the
+    output slots out_off[i] : out_off[i] + n[i]."""
+
+    n: np.ndarray        # int64[count]
+    m: np.ndarray        # int64[count]
+    rp_off: np.ndarray   # int64[count]
+    ci_off: np.ndarray   # int64[count]
+    out_off: np.ndarray  # int64[count]
+    row_ptr: np.ndarray  # int32[sum(n + 1)]
+    col_idx: np.ndarray  # int32[sum(2 m)]
+    specs: list
+
+    @property
+    def count(self) -> int:
+        return len(self.n)
+
+    @property
+    def out_len(self) -> int:
+        return int(self.n.sum())
+
+    def graph(self, i: int) -> Graph:
+        n, a, b = int(self.n[i]), int(self.rp_off[i]), int(self.ci_off[i])
+        m = int(self.m[i])
+        sp = self.specs[i]
+        meta = {"kind": sp.kind, "seed": sp.seed} if sp is not None else {}
+        return Graph(n=n, m=m, row_ptr=self.row_ptr[a:a + n + 1].copy(),
+                     col_idx=self.col_idx[b:b + 2 * m].copy(), name=f"batch_{i}", meta=meta)
+
+
+def batch_specs(count: int, seed: int = 0, n_range=(100, 100_000), deg_range=(4.0, 64.0),
+                gamma_range=(2.1, 2.8)) -> list[GraphSpec]:
+    """Recipes for a mixed batch: n log-uniform in n_range, average degree
+    uniform in deg_range, graphs alternating Erdos-Renyi and Chung-Lu with
+    exponent uniform in gamma_range.  The parameters are drawn with numpy's
+    PCG64 under ``seed``; graph i is generated under seed (seed << 32) + i."""
+    rng = np.random.default_rng(seed)
+    lo, hi = np.log(n_range[0]), np.log(n_range[1])
+    specs = []
+    for i in range(count):
+        n = int(round(float(np.exp(rng.uniform(lo, hi)))))
+        d = float(rng.uniform(*deg_range))
+        g = float(rng.uniform(*gamma_range))
+        gseed = (int(seed) << 32) + i
+        if i % 2 == 0:
+            m = min(int(round(n * d / 2)), n * (n - 1) // 2)
+            specs.append(GraphSpec(KIND_ER, n, m, 0.0, gseed, d))
+        else:
+            specs.append(GraphSpec(KIND_CHUNG_LU, n, int(round(n * d / 2)), g, gseed, d))
+    return specs
+
+
+def make_batch(specs: Sequence[GraphSpec]) -> Batch:
+    """Generate every graph of ``specs`` (in parallel, one graph per thread)
+    and lay them out back to back."""
+    count = len(specs)
+    kind = np.array([s.kind for s in specs], dtype=np.int32)
+    n = np.array([s.n for s in specs], dtype=np.int64)
+    size = np.array([s.size for s in specs], dtype=np.int64)
+    gamma = np.array([s.gamma for s in specs], dtype=np.float64)
+    seeds = np.array([s.seed for s in specs], dtype=np.uint64)
+    m = np.zeros(count, dtype=np.int64)
+    lib = _gen()
+    h = lib.gg_batch_generate(count, _ptr(kind), _ptr(n), _ptr(size), _ptr(gamma), _ptr(seeds),
+                              _ptr(m))
+    if not h:
+        raise ValueError("gg_batch_generate failed (bad recipe or out of memory)")
+    try:
+        rp_off = np.zeros(count, dtype=np.int64)
+        ci_off = np.zeros(count, dtype=np.int64)
+        if count:
+            rp_off[1:] = np.cumsum(n + 1)[:-1]
+            ci_off[1:] = np.cumsum(2 * m)[:-1]
+        out_off = rp_off - np.arange(count, dtype=np.int64)
+        row_ptr = np.empty(max(int((n + 1).sum()), 1), dtype=np.int32)
+        col_idx = np.empty(max(int((2 * m).sum()), 1), dtype=np.int32)
+        if lib.gg_batch_copy(h, _ptr(row_ptr), _ptr(col_idx), _ptr(rp_off), _ptr(ci_off)) != 0:
+            raise ValueError("gg_batch_copy failed")
+    finally:
+        lib.gg_batch_free(h)
+    return Batch(n=n, m=m, rp_off=rp_off, ci_off=ci_off, out_off=out_off, row_ptr=row_ptr,
+                 col_idx=col_idx, specs=list(specs))
+
+
+def concat(graphs: Sequence[Graph]) -> Batch:
+    """Lay out existing graphs back to back as a batch."""
+    count = len(graphs)
+    n = np.array([g.n for g in graphs], dtype=np.int64)
+    m = np.array([g.m for g in graphs], dtype=np.int64)
+    rp_off = np.zeros(count, dtype=np.int64)
+    ci_off = np.zeros(count, dtype=np.int64)
+    if count:
+        rp_off[1:] = np.cumsum(n + 1)[:-1]
+        ci_off[1:] = np.cumsum(2 * m)[:-1]
+    out_off = rp_off - np.arange(count, dtype=np.int64)
+    row_ptr = np.empty(max(int((n + 1).sum()), 1), dtype=np.int32)
+    col_idx = np.empty(max(int((2 * m).sum()), 1), dtype=np.int32)
+    for i, g in enumerate(graphs):
+        row_ptr[rp_off[i]:rp_off[i] + g.n + 1] = g.row_ptr
+        col_idx[ci_off[i]:ci_off[i] + 2 * g.m] = g.col_idx[:2 * g.m]
+    return Batch(n=n, m=m, rp_off=rp_off, ci_off=ci_off, out_off=out_off, row_ptr=row_ptr,
+                 col_idx=col_idx, specs=[None] * count)

@@ -186,8 +186,8 @@ int64_t gg_planted_keys(int64_t n, int64_t k, uint64_t p_fix, uint64_t seed, uin
 /* proportional to w (inverse CDF over the prefix sums).                */
 /* Writes keys[2i], keys[2i+1]; loops become GG_NONE.                   */
 /* ------------------------------------------------------------------ */
-int64_t gg_chung_lu_keys(int64_t n, int64_t npairs, double gamma, uint64_t seed, uint64_t stream,
-                         uint64_t* keys) {
+static int64_t chung_lu_core(int64_t n, int64_t npairs, double gamma, uint64_t seed,
+                             uint64_t stream, uint64_t* keys, int parallel) {
     if (n < 1 || npairs < 0 || !(gamma > 1.0)) return -1;
     double* cdf = (double*)malloc((size_t)n * sizeof(double));
     if (!cdf) return -1;
@@ -199,7 +199,7 @@ int64_t gg_chung_lu_keys(int64_t n, int64_t npairs, double gamma, uint64_t seed,
     }
     const double total = acc;
     const uint64_t base = gg_base(seed, stream);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (parallel)
     for (int64_t p = 0; p < npairs; ++p) {
         uint64_t end[2];
         for (int e = 0; e < 2; ++e) {
@@ -222,6 +222,11 @@ int64_t gg_chung_lu_keys(int64_t n, int64_t npairs, double gamma, uint64_t seed,
     }
     free(cdf);
     return 2 * npairs;
+}
+
+int64_t gg_chung_lu_keys(int64_t n, int64_t npairs, double gamma, uint64_t seed, uint64_t stream,
+                         uint64_t* keys) {
+    return chung_lu_core(n, npairs, gamma, seed, stream, keys, 1);
 }
 
 /* ------------------------------------------------------------------ */
@@ -344,4 +349,135 @@ int32_t gg_keys_to_csr(const uint64_t* keys, int64_t count, int64_t n, int32_t* 
     const int64_t last = count == 0 ? -1 : (int64_t)(keys[count - 1] >> 32);
     for (int64_t q = last + 1; q <= n; ++q) row_ptr[q] = (int32_t)count;
     return bad ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Single-threaded sort + unique and CSR conversion, for building many  */
+/* small graphs at once (one graph per OpenMP thread).                  */
+/* ------------------------------------------------------------------ */
+static int64_t sort_unique_serial(uint64_t* keys, uint64_t* tmp, int64_t count) {
+    int64_t c = 0;
+    for (int64_t i = 0; i < count; ++i)
+        if (keys[i] != GG_NONE) keys[c++] = keys[i];
+    count = c;
+    if (count == 0) return 0;
+    uint64_t orv = 0, andv = ~0ULL;
+    for (int64_t i = 0; i < count; ++i) { orv |= keys[i]; andv &= keys[i]; }
+    const uint64_t vary = orv ^ andv;
+    uint64_t* src = keys;
+    uint64_t* dst = tmp;
+    int64_t cnt[257];
+    for (int d = 0; d < 8; ++d) {
+        const int sh = 8 * d;
+        if (((vary >> sh) & 0xFF) == 0) continue;
+        memset(cnt, 0, sizeof(cnt));
+        for (int64_t i = 0; i < count; ++i) cnt[((src[i] >> sh) & 0xFF) + 1]++;
+        for (int b = 0; b < 256; ++b) cnt[b + 1] += cnt[b];
+        for (int64_t i = 0; i < count; ++i) dst[cnt[(src[i] >> sh) & 0xFF]++] = src[i];
+        uint64_t* sw = src; src = dst; dst = sw;
+    }
+    if (src != keys) memcpy(keys, src, (size_t)count * sizeof(uint64_t));
+    c = 0;
+    for (int64_t i = 0; i < count; ++i)
+        if (i == 0 || keys[i] != keys[i - 1]) keys[c++] = keys[i];
+    return c;
+}
+
+static int32_t keys_to_csr_serial(const uint64_t* keys, int64_t count, int64_t n,
+                                  int32_t* row_ptr, int32_t* col_idx) {
+    int64_t q = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        const uint64_t r = keys[i] >> 32, c = keys[i] & 0xFFFFFFFFULL;
+        if (r >= (uint64_t)n || c >= (uint64_t)n) return -1;
+        while (q <= (int64_t)r) row_ptr[q++] = (int32_t)i;
+        col_idx[i] = (int32_t)c;
+    }
+    while (q <= n) row_ptr[q++] = (int32_t)count;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* A batch of independent graphs.  Graph i is G(n_i, size_i) (kind 0,   */
+/* Erdos-Renyi, same stream as gg_er_keys) or Chung-Lu with size_i      */
+/* pairs and exponent gamma_i (kind 1, same stream as                   */
+/* gg_chung_lu_keys), under seed_i, so it equals the graph the single   */
+/* generators build from the same arguments.  Graphs are generated in   */
+/* parallel, one per thread; gg_batch_copy then places them back to     */
+/* back.                                                                 */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int64_t n, count;
+    int32_t* row_ptr;
+    int32_t* col_idx;
+} gg_one;
+
+typedef struct {
+    int32_t count;
+    gg_one* g;
+} gg_batch;
+
+void gg_batch_free(void* h) {
+    gg_batch* b = (gg_batch*)h;
+    if (!b) return;
+    for (int32_t i = 0; i < b->count; ++i) {
+        free(b->g[i].row_ptr);
+        free(b->g[i].col_idx);
+    }
+    free(b->g);
+    free(b);
+}
+
+void* gg_batch_generate(int32_t count, const int32_t* kind, const int64_t* n, const int64_t* size,
+                        const double* gamma, const uint64_t* seed, int64_t* m_out) {
+    if (count < 0) return NULL;
+    gg_batch* b = (gg_batch*)calloc(1, sizeof(gg_batch));
+    if (!b) return NULL;
+    b->count = count;
+    b->g = (gg_one*)calloc((size_t)(count > 0 ? count : 1), sizeof(gg_one));
+    if (!b->g) { free(b); return NULL; }
+    int fail = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : fail)
+    for (int32_t i = 0; i < count; ++i) {
+        const int64_t nk = 2 * size[i];
+        uint64_t* keys = (uint64_t*)malloc((size_t)(nk > 0 ? nk : 1) * sizeof(uint64_t));
+        uint64_t* tmp = (uint64_t*)malloc((size_t)(nk > 0 ? nk : 1) * sizeof(uint64_t));
+        int64_t cnt = -1;
+        if (keys && tmp) {
+            if (kind[i] == 0)
+                cnt = gg_er_keys(n[i], size[i], seed[i], 1, keys);
+            else if (kind[i] == 1)
+                cnt = chung_lu_core(n[i], size[i], gamma[i], seed[i], 4, keys, 0);
+        }
+        if (cnt >= 0) cnt = sort_unique_serial(keys, tmp, cnt);
+        free(tmp);
+        gg_one* o = &b->g[i];
+        o->n = n[i];
+        o->count = cnt;
+        if (cnt < 0 || cnt > 0x7FFFFFFFLL || n[i] > 0x7FFFFFFELL) {
+            fail = 1;
+        } else {
+            o->row_ptr = (int32_t*)malloc((size_t)(n[i] + 1) * sizeof(int32_t));
+            o->col_idx = (int32_t*)malloc((size_t)(cnt > 0 ? cnt : 1) * sizeof(int32_t));
+            if (!o->row_ptr || !o->col_idx ||
+                keys_to_csr_serial(keys, cnt, n[i], o->row_ptr, o->col_idx) != 0)
+                fail = 1;
+            m_out[i] = cnt / 2;
+        }
+        free(keys);
+    }
+    if (fail) { gg_batch_free(b); return NULL; }
+    return b;
+}
+
+int32_t gg_batch_copy(void* h, int32_t* row_ptr, int32_t* col_idx, const int64_t* rp_off,
+                      const int64_t* ci_off) {
+    gg_batch* b = (gg_batch*)h;
+    if (!b) return -1;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int32_t i = 0; i < b->count; ++i) {
+        const gg_one* o = &b->g[i];
+        memcpy(row_ptr + rp_off[i], o->row_ptr, (size_t)(o->n + 1) * sizeof(int32_t));
+        if (o->count) memcpy(col_idx + ci_off[i], o->col_idx, (size_t)o->count * sizeof(int32_t));
+    }
+    return 0;
 }

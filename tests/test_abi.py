@@ -132,3 +132,98 @@ def test_package_has_no_cpu_fallback():
     assert "oracle" not in src
     for path in (ROOT / "paper_2103_00154_amd").rglob("*.py"):
         assert "import oracle" not in path.read_text(), path
+
+
+# ---------------------------------------------------------------- batches
+
+def test_batch_struct_layouts_match_header(tmp_path):
+    src = tmp_path / "bsizes.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "dsg.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\","
+        "sizeof(dsg_batch_graph), sizeof(dsg_batch_result), sizeof(dsg_batch_launch),"
+        "sizeof(dsg_batch_plan), offsetof(dsg_batch_result, status),"
+        "offsetof(dsg_batch_plan, out_len), offsetof(dsg_batch_plan, reserved));"
+        "return 0;}\n")
+    exe = tmp_path / "bsizes"
+    subprocess.run(["gcc", "-std=c11", f"-I{ROOT / 'include'}", str(src), "-o", str(exe)],
+                   check=True)
+    got = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True,
+                                       check=True).stdout.split()))
+    want = [ctypes.sizeof(dsg.BatchGraph), ctypes.sizeof(dsg.BatchResult),
+            ctypes.sizeof(dsg.BatchLaunch), ctypes.sizeof(dsg.BatchPlan),
+            dsg.BatchResult.status.offset, dsg.BatchPlan.out_len.offset,
+            dsg.BatchPlan.reserved.offset]
+    assert got == want
+    assert dsg.RESULT_WORDS * 8 == ctypes.sizeof(dsg.BatchResult)
+
+
+def test_batch_workspace_bytes():
+    h = dsg.lib()
+    ws = h.dsg_batch_workspace_bytes(4096, 2_000_000_000, 60_000_000)
+    # 24 B per output slot, the table, and 4 B per 256 adjacency entries
+    assert 24 * 60_000_000 + 64 * 4096 + 4 * (2_000_000_000 // 256) <= ws
+    assert ws < 24 * 60_000_000 + 72 * 4096 + 4 * (2_000_000_000 // 256) + 4096
+    assert h.dsg_batch_workspace_bytes(-1, 0, 0) == 0
+    assert h.dsg_batch_workspace_bytes(1, -1, 0) == 0
+    assert h.dsg_batch_workspace_bytes(1, 0, -5) == 0
+    assert h.dsg_batch_workspace_bytes(0, 0, 0) > 0
+
+
+def _prepare(tab, count, rp_len, ci_len, out_len, ws=0x10000, ws_len=None, launch=None):
+    h = dsg.lib()
+    if ws_len is None:
+        ws_len = h.dsg_batch_workspace_bytes(max(count, 0), max(ci_len, 0), max(out_len, 0))
+    plan = dsg.BatchPlan()
+    return h.dsg_batch_prepare(ctypes.addressof(tab) if tab is not None else None, count,
+                               rp_len, ci_len, out_len,
+                               ctypes.byref(launch) if launch is not None else None, ws, ws_len,
+                               None, ctypes.byref(plan))
+
+
+def _table(rows):
+    tab = (dsg.BatchGraph * max(len(rows), 1))()
+    for i, r in enumerate(rows):
+        tab[i] = dsg.BatchGraph(*r)
+    return tab
+
+
+# (row_ptr_off, col_idx_off, out_off, n, m, num, den, reserved); arrays of
+# 20 row_ptr entries, 40 col_idx entries and 16 output slots.  Every case is
+# rejected on the host before the library makes a HIP call.
+@pytest.mark.parametrize("rows,kw,status", [
+    ([(0, 0, 0, 5, 3, 1, 10, 1)], {}, dsg.DSG_EINVAL),            # reserved != 0
+    ([(0, 0, 0, -1, 0, 1, 10, 0)], {}, dsg.DSG_EINVAL),           # n < 0
+    ([(0, 0, 0, 5, 3, 1, 0, 0)], {}, dsg.DSG_EINVAL),             # den < 1
+    ([(16, 0, 0, 5, 3, 1, 10, 0)], {}, dsg.DSG_EINVAL),           # row_ptr range
+    ([(0, 36, 0, 5, 3, 1, 10, 0)], {}, dsg.DSG_EINVAL),           # col_idx range
+    ([(0, 0, 12, 5, 3, 1, 10, 0)], {}, dsg.DSG_EINVAL),           # output range
+    ([(0, 0, 0, 5, 3, 1, 10, 0), (6, 6, 4, 5, 3, 1, 10, 0)], {}, dsg.DSG_EINVAL),  # overlap
+    ([(0, 0, 0, 5, 3, 1, 10, 0)], {"ws_len": 64}, dsg.DSG_EINVAL),                # short ws
+    ([(0, 0, 0, 5, 3, 1, 10, 0)], {"ws": 0x10001}, dsg.DSG_EINVAL),               # misaligned
+    ([(0, 0, 0, 5, 3, 1, 10, 0)], {"ws": None}, dsg.DSG_EINVAL),
+    ([(0, 0, 0, 5, 3, 1, 10, 0)], {"launch": dsg.BatchLaunch(300, 0, 0, 0)}, dsg.DSG_EINVAL),
+    ([(0, 0, 0, 5, 3, 1, 10, 0)], {"launch": dsg.BatchLaunch(1024, 0, 0, 16)}, dsg.DSG_EINVAL),
+    ([(0, 0, 0, 5, 3, 1, 10, 0)], {"launch": dsg.BatchLaunch(0, 9, 0, 0)}, dsg.DSG_EINVAL),
+    ([(0, 0, 0, 5, 3, 1 << 62, 1 << 62, 0)], {}, dsg.DSG_EOVERFLOW),
+    ([(0, 0, 0, 2**31, 3, 1, 10, 0)], {}, dsg.DSG_EOVERFLOW),
+])
+def test_batch_prepare_argument_errors(rows, kw, status):
+    assert _prepare(_table(rows), len(rows), 20, 40, 16, **kw) == status
+
+
+def test_batch_prepare_null_arguments():
+    h = dsg.lib()
+    assert _prepare(None, 1, 20, 40, 16) == dsg.DSG_EINVAL
+    assert _prepare(_table([]), -1, 20, 40, 16) == dsg.DSG_EINVAL
+    tab = _table([(0, 0, 0, 5, 3, 1, 10, 0)])
+    assert h.dsg_batch_prepare(ctypes.addressof(tab), 1, 20, 40, 16, None, 0x10000, 1 << 20,
+                               None, None) == dsg.DSG_EINVAL
+
+
+def test_batch_run_rejects_unprepared_plan():
+    h = dsg.lib()
+    plan = dsg.BatchPlan()
+    assert h.dsg_batch_run(ctypes.byref(plan), 0x1000, 0x2000, None, None, 0x3000,
+                           None) == dsg.DSG_EINVAL
+    assert h.dsg_batch_run(None, 0x1000, 0x2000, None, None, 0x3000, None) == dsg.DSG_EINVAL

@@ -74,3 +74,46 @@ def test_counter_rng_fixed_values():
     vals = [inputs.draw_for_test(0, 1, i) for i in range(3)]
     assert len(set(vals)) == 3
     assert vals == [inputs.draw_for_test(0, 1, i) for i in range(3)]
+
+
+# ---------------------------------------------------------------- batches
+
+def test_batch_graphs_equal_the_single_generators():
+    specs = inputs.batch_specs(24, seed=2, n_range=(100, 3000))
+    b = inputs.make_batch(specs)
+    assert b.count == 24 and b.out_len == sum(s.n for s in specs)
+    assert {s.kind for s in specs} == {inputs.KIND_ER, inputs.KIND_CHUNG_LU}
+    for i, s in enumerate(specs):
+        g = b.graph(i)
+        if s.kind == inputs.KIND_ER:
+            ref = inputs.erdos_renyi(s.n, s.size, s.seed)
+        else:
+            ref = inputs.chung_lu(s.n, s.avg_deg, s.gamma, s.seed)
+        assert g.n == ref.n and g.m == ref.m
+        assert np.array_equal(g.row_ptr, ref.row_ptr)
+        assert np.array_equal(g.col_idx, ref.col_idx)
+
+
+def test_batch_specs_follow_the_recipe():
+    specs = inputs.batch_specs(400, seed=0)
+    n = np.array([s.n for s in specs])
+    assert n.min() >= 100 and n.max() <= 100_000
+    # log-uniform: about half of the graphs below the geometric midpoint
+    assert 150 < np.count_nonzero(n < np.sqrt(100 * 100_000)) < 250
+    d = np.array([s.avg_deg for s in specs])
+    assert d.min() >= 4 and d.max() <= 64
+    g = np.array([s.gamma for s in specs if s.kind == inputs.KIND_CHUNG_LU])
+    assert len(g) == 200 and g.min() >= 2.1 and g.max() <= 2.8
+    assert specs[5].seed == 5 and inputs.batch_specs(3, seed=1)[2].seed == (1 << 32) + 2
+
+
+def test_concat_round_trips_and_offsets_are_disjoint():
+    gs = [inputs.empty(0), inputs.clique(5), inputs.path(7), inputs.empty(3), inputs.star(9)]
+    b = inputs.concat(gs)
+    for i, g in enumerate(gs):
+        h = b.graph(i)
+        assert (h.n, h.m) == (g.n, g.m)
+        assert np.array_equal(h.row_ptr, g.row_ptr)
+        assert np.array_equal(h.col_idx, g.col_idx[:2 * g.m])
+    ends = b.out_off + b.n
+    assert np.all(ends[:-1] <= b.out_off[1:]) and ends[-1] == b.out_len
