@@ -157,13 +157,11 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
         int64_t S = n, E = m2 / 2, bE = E, bS = S;
         int32_t pass = 0, bp = 0, status = DSG_OK, found = 0;
 
-        // the row offsets must run from 0 to 2m without decreasing
-        if (n > 0) {
-            int32_t bad = (rp[0] != 0 || rp[n] != m2) ? 1 : 0;
-            for (int32_t v = tid; v < n && !bad; v += NT) bad = rp[v] > rp[v + 1];
-            if (tid == 0) s_nslots = 0;
-            if (__syncthreads_or(bad)) status = DSG_EINVAL;
-        }
+        // the row offsets must run from 0 to 2m; that they never decrease
+        // is checked by the first mark, chunk by chunk, before any use
+        if (n > 0 && (rp[0] != 0 || rp[n] != m2)) status = DSG_EINVAL;
+        if (tid == 0) s_nslots = 0;
+        __syncthreads();
 
         while (status == DSG_OK && S > 0) {
             ++pass;
@@ -179,34 +177,49 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
             for (int32_t base = 0; base < nlive; base += CH) {
                 int32_t v[kBMarkItems], d[kBMarkItems], rs[kBMarkItems], rl[kBMarkItems];
                 const int32_t i0 = base + tid * kBMarkItems;
+                // loads first (clamped indices, no load inside a branch)
+                if (pass == 1) {
+                    int32_t re[kBMarkItems];
 #pragma unroll
-                for (int j = 0; j < kBMarkItems; ++j) {
-                    const int32_t i = i0 + j;
-                    v[j] = -1;
-                    d[j] = 0;
-                    rs[j] = 0;
-                    rl[j] = 0;
-                    if (i < nlive) {
-                        if (pass == 1) {
-                            v[j] = i;
-                            rs[j] = rp[i];
-                            rl[j] = rp[i + 1] - rs[j];
-                            d[j] = rl[j];
-                        } else {
-                            v[j] = live[i];
-                        }
+                    for (int j = 0; j < kBMarkItems; ++j) {
+                        const int32_t i = min(i0 + j, nlive - 1);
+                        rs[j] = rp[i];
+                        re[j] = rp[i + 1];
                     }
-                }
-                if (pass > 1) {
+                    // with row_ptr[0] = 0, a row that ends beyond 2m or
+                    // before it starts is the first sign of bad offsets;
+                    // rows before it are valid, so nothing was misused yet
+                    int32_t bad = 0;
 #pragma unroll
-                    for (int j = 0; j < kBMarkItems; ++j)
-                        if (v[j] >= 0) d[j] = live_degree(v[j], cap, st16, s_big, gdeg);
+                    for (int j = 0; j < kBMarkItems; ++j) {
+                        const bool ok = i0 + j < nlive;
+                        v[j] = ok ? i0 + j : -1;
+                        rl[j] = re[j] - rs[j];
+                        d[j] = rl[j];
+                        if (ok && (rl[j] < 0 || re[j] > m2)) bad = 1;
+                    }
+                    if (__syncthreads_or(bad)) {
+                        status = DSG_EINVAL;
+                        break;
+                    }
+                } else {
 #pragma unroll
-                    for (int j = 0; j < kBMarkItems; ++j)
-                        if (v[j] >= 0 && d[j] > 0 && d[j] <= T) {
-                            rs[j] = rp[v[j]];
-                            rl[j] = rp[v[j] + 1] - rs[j];
-                        }
+                    for (int j = 0; j < kBMarkItems; ++j) v[j] = live[min(i0 + j, nlive - 1)];
+#pragma unroll
+                    for (int j = 0; j < kBMarkItems; ++j) {
+                        if (i0 + j >= nlive) v[j] = -1;
+                        d[j] = v[j] >= 0 ? live_degree(v[j], cap, st16, s_big, gdeg) : 0;
+                    }
+                    int32_t re[kBMarkItems];
+#pragma unroll
+                    for (int j = 0; j < kBMarkItems; ++j) {
+                        // row bounds of the failures (a harmless row 0 otherwise)
+                        const int32_t x = (v[j] >= 0 && d[j] > 0 && d[j] <= T) ? v[j] : 0;
+                        rs[j] = rp[x];
+                        re[j] = rp[x + 1];
+                    }
+#pragma unroll
+                    for (int j = 0; j < kBMarkItems; ++j) rl[j] = re[j] - rs[j];
                 }
                 uint32_t cA = 0, cL = 0, sl = 0;
 #pragma unroll
@@ -277,8 +290,18 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
                 nL += (int32_t)(tot >> 48);
                 W += (int32_t)(uint32_t)tot;
             }
-            __threadfence();
+            if (status != DSG_OK) break;
             __syncthreads();
+            // degrees in device memory are updated with device atomics and
+            // read with L1-bypassing loads: order them at device scope.
+            // Graphs whose state is all in LDS need only the barrier (one
+            // workgroup owns a graph, and its plain stores and loads meet
+            // in the CU's own cache).  The slot count is final after pass 1.
+            const bool dev_state = n > cap || s_nslots > kSlots;
+            if (dev_state) {
+                __threadfence();
+                __syncthreads();
+            }
 
             // ------------------------------------------------ walk
             uint32_t cross = 0, intra = 0, badc = 0;
@@ -289,11 +312,20 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
                     const int32_t t0 = t * WT;
                     const int32_t len = min(WT, W - t0);
                     const int32_t rc = tf[t];
-                    // rows that start inside the tile: mark their first entry
-                    for (int32_t r = rc + 1 + lane; r < nA; r += 64) {
-                        const int32_t s = apre[r];
-                        if (s >= t0 + len) break;
-                        own[s - t0] = r;
+                    // rows that start inside the tile: mark their first
+                    // entry (256 rows per step, loads first)
+                    for (int32_t r0 = rc + 1; r0 < nA; r0 += 256) {
+                        int32_t st[4];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) st[k] = apre[min(r0 + 64 * k + lane, nA - 1)];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const int32_t r = r0 + 64 * k + lane;
+                            if (r < nA && st[k] < t0 + len) own[st[k] - t0] = r;
+                        }
+                        // rows start in increasing order: stop once the last
+                        // row of this step lies beyond the tile
+                        if (__shfl(st[3], 63, 64) >= t0 + len) break;
                     }
                     wave_sync();
                     // owner of every entry: running max over the marks (rows
@@ -323,52 +355,72 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
                                               max(row[4 * k + 2], carry), max(row[4 * k + 3], carry));
                     }
                     wave_sync();
-                    // neighbour ids, consecutive lanes on consecutive entries
+                    // neighbour ids, consecutive lanes on consecutive
+                    // entries.  Every stage issues all of its loads before
+                    // the next stage needs them (no load inside a branch):
+                    // lanes past the tile end re-read its last entry.
                     int32_t u[IT];
+                    {
+                        int32_t rw[IT], ab[IT];
+#pragma unroll
+                        for (int j = 0; j < IT; ++j) rw[j] = own[min(j * 64 + lane, len - 1)];
+#pragma unroll
+                        for (int j = 0; j < IT; ++j) ab[j] = abase[rw[j]];
+#pragma unroll
+                        for (int j = 0; j < IT; ++j)
+                            u[j] = __builtin_nontemporal_load(ci + ab[j] + t0 +
+                                                              min(j * 64 + lane, len - 1));
+                    }
+                    // states: the LDS word for ids below cap, the removal
+                    // pass (device memory) above
+                    uint32_t sv[IT];
 #pragma unroll
                     for (int j = 0; j < IT; ++j) {
-                        const int p = j * 64 + lane;
-                        u[j] = -1;
-                        if (p < len) {
-                            const int32_t pos = abase[own[p]] + t0 + p;
-                            u[j] = __builtin_nontemporal_load(ci + pos);
+                        const int32_t x = u[j];
+                        const bool in = (uint32_t)x < (uint32_t)cap;
+                        const uint32_t st = st16[in ? x : 0];
+                        sv[j] = in ? st : kStDead;
+                    }
+                    int32_t rv[IT];
+#pragma unroll
+                    for (int j = 0; j < IT; ++j) rv[j] = 0;
+                    if (n > cap) {
+#pragma unroll
+                        for (int j = 0; j < IT; ++j) {
+                            const int32_t x = u[j];
+                            rv[j] = rem[(x >= cap && x < n) ? x : 0];
                         }
                     }
-                    wave_sync();
 #pragma unroll
                     for (int j = 0; j < IT; ++j) {
-                        const int p = j * 64 + lane;
-                        if (p >= len) continue;
                         const int32_t x = u[j];
+                        if (j * 64 + lane >= len) continue;
                         if ((uint32_t)x >= (uint32_t)n) {
                             ++badc;
                         } else if (x < cap) {
-                            const uint32_t s = st16[x];
-                            if (s < kStSlot0) {
+                            const uint32_t st = sv[j];
+                            if (st < kStSlot0) {
                                 atomicSub(&s_state[x >> 1], 1u << ((x & 1) << 4));
                                 ++cross;
-                            } else if (s < kStGlobal) {
-                                atomicSub(&s_big[s - kStSlot0], 1);
+                            } else if (st < kStGlobal) {
+                                atomicSub(&s_big[st - kStSlot0], 1);
                                 ++cross;
-                            } else if (s == kStGlobal) {
+                            } else if (st == kStGlobal) {
                                 dec_global(gdeg + x);
                                 ++cross;
-                            } else if (s == kStNow) {
+                            } else if (st == kStNow) {
                                 ++intra;
                             }
-                        } else {
-                            const int32_t r = rem[x];
-                            if (r == kNever) {
-                                dec_global(gdeg + x);
-                                ++cross;
-                            } else if (r == pass) {
-                                ++intra;
-                            }
+                        } else if (rv[j] == kNever) {
+                            dec_global(gdeg + x);
+                            ++cross;
+                        } else if (rv[j] == pass) {
+                            ++intra;
                         }
                     }
                 }
             }
-            __threadfence();
+            if (dev_state) __threadfence();
             const unsigned long long ci_sum = block_sum<unsigned long long, NW>(
                 (unsigned long long)cross | ((unsigned long long)intra << 32), s_red64);
             const uint32_t bad_sum = block_sum<uint32_t, NW>(badc, s_red32);
@@ -393,9 +445,13 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
                 bp = pass;
             }
             // this pass's failures are gone from the next pass on
-            for (int32_t r = tid; r < nA; r += NT) {
-                const int32_t x = alist[r];
-                if (x < cap) st16[x] = (uint16_t)kStDead;
+            for (int32_t r = tid; r < nA; r += 4 * NT) {
+                int32_t x[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) x[k] = alist[min(r + k * NT, nA - 1)];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (r + k * NT < nA && x[k] < cap) st16[x[k]] = (uint16_t)kStDead;
             }
         }
 
@@ -405,10 +461,12 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
             for (int32_t base = 0; base < n; base += CH) {
                 const int32_t i0 = base + tid * kBMarkItems;
                 uint32_t keep = 0, c = 0;
+                int32_t ra[kBMarkItems];
+#pragma unroll
+                for (int j = 0; j < kBMarkItems; ++j) ra[j] = rem[min(i0 + j, n - 1)];
 #pragma unroll
                 for (int j = 0; j < kBMarkItems; ++j) {
-                    const int32_t i = i0 + j;
-                    if (i < n && rem[i] > bp) {
+                    if (i0 + j < n && ra[j] > bp) {
                         keep |= 1u << j;
                         ++c;
                     }
