@@ -259,11 +259,12 @@ typedef struct {
     int64_t reserved[4];
 } dsg_batch_plan;
 
-/* Device workspace bytes for a batch of `count` graphs whose adjacency
- * arrays hold col_idx_len entries and whose output slots span out_len
- * entries: 24 bytes per slot, 64 + 8 bytes per graph and 4 bytes per 256
- * adjacency entries; 0 for invalid sizes. */
-size_t dsg_batch_workspace_bytes(int32_t count, int64_t col_idx_len, int64_t out_len);
+/* Device workspace bytes for a batch of `count` graphs with `entries`
+ * adjacency entries in total (the sum of 2m over the batch) whose output
+ * slots span out_len entries: 24 bytes per slot, 64 bytes per graph and
+ * 4 bytes per 256 adjacency entries (plus 8 per graph); 0 for invalid
+ * sizes. */
+size_t dsg_batch_workspace_bytes(int32_t count, int64_t entries, int64_t out_len);
 
 /*
  * Check a batch on the host, order it for the device queue and upload its
@@ -275,7 +276,7 @@ size_t dsg_batch_workspace_bytes(int32_t count, int64_t col_idx_len, int64_t out
  *                entries of the caller's row_ptr, col_idx and best_ids /
  *                removed_at arrays; every graph's ranges must lie inside.
  *   launch       host or NULL.
- *   workspace    device, >= dsg_batch_workspace_bytes(count, col_idx_len,
+ *   workspace    device, >= dsg_batch_workspace_bytes(count, sum of 2m,
  *                out_len) bytes, 256-byte aligned.
  *
  * Errors: DSG_EINVAL for NULL pointers, count < 0, a short or misaligned

@@ -81,7 +81,8 @@ def tune_batch(table, count: int, rp_len: int, ci_len: int, out_len: int, rp, ci
                 return dict(stored), []
     best = torch.empty(max(out_len, 1), dtype=torch.int32, device=rp.device)
     res = torch.empty((max(count, 1), dsg.RESULT_WORDS), dtype=torch.int64, device=rp.device)
-    workspace = torch.empty(dsg.batch_workspace_bytes(count, ci_len, out_len), dtype=torch.uint8,
+    entries = sum(2 * int(table[i].m) for i in range(count))
+    workspace = torch.empty(dsg.batch_workspace_bytes(count, entries, out_len), dtype=torch.uint8,
                             device=rp.device)
     timings = []
     for launch in candidates:

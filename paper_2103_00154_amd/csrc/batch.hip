@@ -543,7 +543,7 @@ struct BLayout {
     size_t head, table, tf, gdeg, live, alist, apre, abase, rem, total;
 };
 
-BLayout batch_layout(int64_t count, int64_t ci_len, int64_t out_len) {
+BLayout batch_layout(int64_t count, int64_t entries, int64_t out_len) {
     BLayout L;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -553,7 +553,7 @@ BLayout batch_layout(int64_t count, int64_t ci_len, int64_t out_len) {
     };
     L.head = take(sizeof(BHead));
     L.table = take(sizeof(BGraph) * (size_t)count);
-    L.tf = take(4 * (size_t)(ci_len / kMinWaveTile + 2 * count + 1));
+    L.tf = take(4 * (size_t)(entries / kMinWaveTile + 2 * count + 1));
     L.gdeg = take(4 * (size_t)out_len);
     L.live = take(4 * (size_t)out_len);
     L.alist = take(4 * (size_t)out_len);
@@ -602,10 +602,10 @@ using namespace dsg;
 
 extern "C" {
 
-size_t dsg_batch_workspace_bytes(int32_t count, int64_t col_idx_len, int64_t out_len) {
-    if (count < 0 || col_idx_len < 0 || out_len < 0) return 0;
-    if (out_len > ((int64_t)1 << 40) || col_idx_len > ((int64_t)1 << 42)) return 0;
-    return batch_layout(count, col_idx_len, out_len).total;
+size_t dsg_batch_workspace_bytes(int32_t count, int64_t entries, int64_t out_len) {
+    if (count < 0 || entries < 0 || out_len < 0) return 0;
+    if (out_len > ((int64_t)1 << 40) || entries > ((int64_t)1 << 42)) return 0;
+    return batch_layout(count, entries, out_len).total;
 }
 
 int32_t dsg_batch_prepare(const dsg_batch_graph* graphs, int32_t count, int64_t row_ptr_len,
@@ -613,9 +613,7 @@ int32_t dsg_batch_prepare(const dsg_batch_graph* graphs, int32_t count, int64_t 
                           void* workspace, size_t ws_bytes, void* stream, dsg_batch_plan* plan) {
     if (!plan || count < 0 || (count > 0 && !graphs)) return DSG_EINVAL;
     if (row_ptr_len < 0 || col_idx_len < 0 || out_len < 0) return DSG_EINVAL;
-    const size_t need = dsg_batch_workspace_bytes(count, col_idx_len, out_len);
-    if (need == 0 || !workspace || ws_bytes < need || ((uintptr_t)workspace & 255u))
-        return DSG_EINVAL;
+    if (!workspace || ((uintptr_t)workspace & 255u)) return DSG_EINVAL;
 
     int32_t block = 1024, bpc = 1, items = 8, grid = 0;
     if (launch) {
@@ -630,7 +628,7 @@ int32_t dsg_batch_prepare(const dsg_batch_graph* graphs, int32_t count, int64_t 
     std::vector<BGraph> tab((size_t)count);
     std::vector<std::pair<int64_t, int64_t>> outs;
     outs.reserve((size_t)count);
-    int64_t tf_at = 0;
+    int64_t tf_at = 0, entries = 0;
     for (int32_t i = 0; i < count; ++i) {
         const dsg_batch_graph& g = graphs[i];
         if (g.reserved != 0) return DSG_EINVAL;
@@ -649,6 +647,7 @@ int32_t dsg_batch_prepare(const dsg_batch_graph* graphs, int32_t count, int64_t 
         b.out_off = g.out_off;
         b.tf_off = tf_at;
         tf_at += 2 * g.m / kMinWaveTile + 2;
+        entries += 2 * g.m;
         b.num = g.eps_num;
         b.den = g.eps_den;
         b.n = (int32_t)g.n;
@@ -656,6 +655,8 @@ int32_t dsg_batch_prepare(const dsg_batch_graph* graphs, int32_t count, int64_t 
         b.max_pass = pass_bound(g.n, g.eps_num, g.eps_den);
         b.index = i;
     }
+    const size_t need = dsg_batch_workspace_bytes(count, entries, out_len);
+    if (need == 0 || ws_bytes < need) return DSG_EINVAL;
     std::sort(outs.begin(), outs.end());
     for (size_t i = 1; i < outs.size(); ++i)
         if (outs[i - 1].first + outs[i - 1].second > outs[i].first) return DSG_EINVAL;
@@ -680,7 +681,7 @@ int32_t dsg_batch_prepare(const dsg_batch_graph* graphs, int32_t count, int64_t 
                             (int)(di.lds_per_block - (int64_t)attr.sharedSizeBytes));
     if (e != hipSuccess) return map_hip(e);
 
-    const BLayout L = batch_layout(count, col_idx_len, out_len);
+    const BLayout L = batch_layout(count, entries, out_len);
     char* base = static_cast<char*>(workspace);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (count > 0) {
@@ -703,7 +704,7 @@ int32_t dsg_batch_prepare(const dsg_batch_graph* graphs, int32_t count, int64_t 
     plan->workspace = workspace;
     plan->ws_bytes = need;
     plan->reserved[0] = (int64_t)kPlanMagic;
-    plan->reserved[1] = col_idx_len;
+    plan->reserved[1] = entries;
     return DSG_OK;
 }
 

@@ -280,8 +280,10 @@ def validate_csr(row_ptr, col_idx, m: int | None = None, stream=None) -> int:
 RESULT_WORDS = ctypes.sizeof(BatchResult) // 8
 
 
-def batch_workspace_bytes(count: int, col_idx_len: int, out_len: int) -> int:
-    return int(lib().dsg_batch_workspace_bytes(count, col_idx_len, out_len))
+def batch_workspace_bytes(count: int, entries: int, out_len: int) -> int:
+    """Workspace bytes for `count` graphs with `entries` adjacency entries in
+    total (sum of 2m) and out_len output slots."""
+    return int(lib().dsg_batch_workspace_bytes(count, entries, out_len))
 
 
 def batch_table(n, m, row_ptr_off, col_idx_off, out_off, eps):
@@ -308,7 +310,8 @@ class Batch:
         self.count = count
         self.out_len = out_len
         dev = torch.device(device or "cuda")
-        nbytes = batch_workspace_bytes(count, col_idx_len, out_len)
+        self.entries = sum(2 * int(table[i].m) for i in range(count))
+        nbytes = batch_workspace_bytes(count, self.entries, out_len)
         if nbytes == 0:
             raise DsgError(DSG_EINVAL, "dsg_batch_workspace_bytes")
         if workspace is None:

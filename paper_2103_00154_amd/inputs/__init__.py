@@ -320,6 +320,24 @@ def batch_specs(count: int, seed: int = 0, n_range=(100, 100_000), deg_range=(4.
     return specs
 
 
+def serving_specs(count: int, seed: int = 0, median: float = 20_000, sigma: float = 1.0,
+                  n_cap: int = 2_000_000, deg_range=(8.0, 64.0),
+                  gamma_range=(2.1, 2.8)) -> list[GraphSpec]:
+    """Recipes of request graphs: Chung-Lu with n lognormal (the given median
+    and sigma, clipped to [100, n_cap]), average degree uniform in deg_range
+    and exponent uniform in gamma_range; numpy PCG64 under ``seed``, graph i
+    generated under seed (seed << 32) + (1 << 31) + i."""
+    rng = np.random.default_rng(seed + 0x5E5)
+    specs = []
+    for i in range(count):
+        n = int(min(max(round(float(rng.lognormal(np.log(median), sigma))), 100), n_cap))
+        d = float(rng.uniform(*deg_range))
+        g = float(rng.uniform(*gamma_range))
+        specs.append(GraphSpec(KIND_CHUNG_LU, n, int(round(n * d / 2)), g,
+                               (int(seed) << 32) + (1 << 31) + i, d))
+    return specs
+
+
 def make_batch(specs: Sequence[GraphSpec]) -> Batch:
     """Generate every graph of ``specs`` (in parallel, one graph per thread)
     and lay them out back to back."""

@@ -1,0 +1,301 @@
+"""Serving loop: peel requests that arrive over time, batched as they come.
+
+A request is one graph (CSR in pinned host memory) and one eps.  The server
+owns one device arena - its HBM budget - and admits waiting requests in
+arrival order while their footprint fits: the graph's CSR, its output slots
+and its share of the batch workspace (dsg_batch_workspace_bytes).  Admitted
+requests are uploaded into the arena, where the CSR stays resident until the
+request completes, and are peeled by the persistent batch kernel
+(dsg_batch_run) as one micro-batch on one of several HIP streams.  Requests
+that arrive while earlier micro-batches are still on the device are admitted
+as soon as a stream and memory are free, so their work overlaps on the device
+with the batches already running (continuous batching).  Completed batches
+free their memory, and their results are read back.
+
+Every result is exactly the result of peeling the graph alone: the kernels
+are exact integer code and a graph is peeled by one workgroup, independently
+of what else shares the launch.
+"""
+from __future__ import annotations
+
+import bisect
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import dsg
+
+ALIGN = 256
+
+
+class Arena:
+    """First-fit allocator over [0, size) bytes, 256-byte granules; host-side
+    bookkeeping for one device buffer."""
+
+    def __init__(self, size: int):
+        self.size = size - size % ALIGN
+        self._free = [(0, self.size)]  # sorted (offset, length)
+        self.used = 0
+        self.peak = 0
+
+    def alloc(self, nbytes: int) -> int | None:
+        need = max(ALIGN, (nbytes + ALIGN - 1) // ALIGN * ALIGN)
+        for i, (off, ln) in enumerate(self._free):
+            if ln >= need:
+                if ln == need:
+                    del self._free[i]
+                else:
+                    self._free[i] = (off + need, ln - need)
+                self.used += need
+                self.peak = max(self.peak, self.used)
+                return off
+        return None
+
+    def free(self, off: int, nbytes: int) -> None:
+        ln = max(ALIGN, (nbytes + ALIGN - 1) // ALIGN * ALIGN)
+        i = bisect.bisect_left(self._free, (off, 0))
+        self._free.insert(i, (off, ln))
+        self.used -= ln
+        # coalesce with the neighbours
+        if i + 1 < len(self._free) and off + ln == self._free[i + 1][0]:
+            self._free[i] = (off, ln + self._free[i + 1][1])
+            del self._free[i + 1]
+        if i > 0 and self._free[i - 1][0] + self._free[i - 1][1] == off:
+            po, pl = self._free[i - 1]
+            self._free[i - 1] = (po, pl + self._free[i][1])
+            del self._free[i]
+
+    def largest_free(self) -> int:
+        return max((ln for _, ln in self._free), default=0)
+
+
+@dataclass
+class HostGraph:
+    """A request graph in pinned host memory: row_ptr (n+1) then col_idx (2m)."""
+
+    n: int
+    m: int
+    csr: object  # pinned torch.int32 tensor of n + 1 + 2m entries
+
+    @staticmethod
+    def from_graph(g) -> "HostGraph":
+        import torch
+        buf = np.empty(g.n + 1 + 2 * g.m, dtype=np.int32)
+        buf[:g.n + 1] = g.row_ptr
+        buf[g.n + 1:] = g.col_idx[:2 * g.m]
+        return HostGraph(g.n, g.m, torch.from_numpy(buf).pin_memory())
+
+
+@dataclass
+class Request:
+    rid: int
+    graph: HostGraph
+    eps: tuple
+    arrival: float                # seconds since the start of the run
+    admitted: float = -1.0
+    done: float = -1.0
+    result: dict | None = None
+    best: np.ndarray | None = None
+
+
+@dataclass
+class _MicroBatch:
+    reqs: list
+    stream: object
+    event: object
+    allocs: list                  # (offset, bytes) in the arena
+    res_host: object
+    best_host: object
+    best_off: list = field(default_factory=list)
+    res_dev: object = None
+
+
+def footprint(n: int, m: int) -> int:
+    """Arena bytes one request holds while admitted: its CSR, its output
+    slots and its part of the batch workspace (per-vertex arrays, table row
+    and tile table), each rounded to the arena granule."""
+    def r(x):
+        return (x + ALIGN - 1) // ALIGN * ALIGN
+    return r(4 * (n + 1 + 2 * m)) + r(4 * n) + 24 * n + 72 + 4 * (2 * m // 256 + 2) + 6 * ALIGN
+
+
+class Server:
+    """Continuous-batching peel server on one device (see the module doc)."""
+
+    def __init__(self, budget_bytes: int, *, streams: int = 4, max_batch: int = 512,
+                 launch: dict | None = None, device=None):
+        import torch
+        self.device = torch.device(device or "cuda")
+        self.buf = torch.empty(budget_bytes, dtype=torch.uint8, device=self.device)
+        self.arena = Arena(budget_bytes)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
+        self.busy = [None] * streams
+        self.waiting: deque[Request] = deque()
+        self.max_batch = max_batch
+        self.launch = launch
+        self.completed: list[Request] = []
+        self.batches = 0
+        self.batch_sizes: list[int] = []
+        self.max_in_flight = 0
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def submit(self, req: Request) -> None:
+        if footprint(req.graph.n, req.graph.m) > self.arena.size:
+            raise ValueError(f"request {req.rid} needs more memory than the whole budget")
+        self.waiting.append(req)
+
+    @property
+    def idle(self) -> bool:
+        return not self.waiting and all(b is None for b in self.busy)
+
+    # ------------------------------------------------------------------
+    def _reap(self) -> None:
+        for k, mb in enumerate(self.busy):
+            if mb is None or not mb.event.query():
+                continue
+            t = self.now()
+            results = dsg.Batch.results(mb.res_host)
+            best = mb.best_host.numpy()
+            for i, rq in enumerate(mb.reqs):
+                rq.done = t
+                rq.result = results[i]
+                a = mb.best_off[i]
+                rq.best = best[a:a + rq.result["best_size"]].copy()
+                self.completed.append(rq)
+            for off, nb in mb.allocs:
+                self.arena.free(off, nb)
+            self.busy[k] = None
+
+    def _shared_bytes(self, take) -> tuple[int, int]:
+        sum_n = sum(r.graph.n for r in take)
+        sum_e = sum(2 * r.graph.m for r in take)
+        return dsg.batch_workspace_bytes(len(take), sum_e, sum_n), 4 * max(sum_n, 1)
+
+    def _try_place(self, sizes) -> list | None:
+        got = []
+        for nb in sizes:
+            off = self.arena.alloc(nb)
+            if off is None:
+                for o, b in got:
+                    self.arena.free(o, b)
+                return None
+            got.append((off, nb))
+        return got
+
+    def _launch(self, k: int) -> None:
+        import torch
+        take, allocs = [], []
+        # admit in arrival order while the request's CSR and the batch's
+        # shared regions (workspace, output slots) fit; the head request
+        # waits for memory when it does not
+        while self.waiting and len(take) < self.max_batch:
+            rq = self.waiting[0]
+            nb = 4 * (rq.graph.n + 1 + 2 * rq.graph.m)
+            off = self.arena.alloc(nb)
+            if off is None:
+                break
+            trial = self._try_place(self._shared_bytes(take + [rq]))
+            if trial is None:
+                self.arena.free(off, nb)
+                break
+            for o, b in trial:
+                self.arena.free(o, b)
+            allocs.append((off, nb))
+            take.append(self.waiting.popleft())
+        if not take:
+            return
+        csr_off = [o for o, _ in allocs]
+        sum_n = sum(r.graph.n for r in take)
+        ws_bytes, best_bytes = self._shared_bytes(take)
+        (ws_off, _), (best_off, _) = self._try_place((ws_bytes, best_bytes))
+        allocs += [(ws_off, ws_bytes), (best_off, best_bytes)]
+        now = self.now()
+        for rq in take:
+            rq.admitted = now
+        s = self.streams[k]
+        ints = self.buf.view(torch.int32)
+        n_arr = [r.graph.n for r in take]
+        m_arr = [r.graph.m for r in take]
+        rp_off = [o // 4 for o in csr_off]
+        ci_off = [o // 4 + r.graph.n + 1 for o, r in zip(csr_off, take)]
+        out = np.zeros(len(take), dtype=np.int64)
+        if len(take) > 1:
+            out[1:] = np.cumsum(n_arr)[:-1]
+        eps = [r.eps for r in take]
+        tab, count = dsg.batch_table(n_arr, m_arr, rp_off, ci_off, out, eps)
+        ws = self.buf[ws_off:ws_off + ws_bytes]
+        with torch.cuda.stream(s):
+            plan = dsg.Batch(tab, count, ints.numel(), ints.numel(), sum_n, launch=self.launch,
+                             workspace=ws, device=self.device, stream=s)
+            for o, r in zip(csr_off, take):
+                ints[o // 4:o // 4 + r.graph.csr.numel()].copy_(r.graph.csr, non_blocking=True)
+            best = ints[best_off // 4:best_off // 4 + max(sum_n, 1)]
+            res = torch.empty((count, dsg.RESULT_WORDS), dtype=torch.int64, device=self.device)
+            plan.run(ints, ints, best_ids=best, results=res, stream=s)
+            res_host = torch.empty(res.shape, dtype=torch.int64, pin_memory=True)
+            res_host.copy_(res, non_blocking=True)
+            best_host = torch.empty(best.numel(), dtype=torch.int32, pin_memory=True)
+            best_host.copy_(best, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        self.busy[k] = _MicroBatch(take, s, ev, allocs, res_host, best_host, list(out), res)
+        self.batches += 1
+        self.batch_sizes.append(len(take))
+        self.max_in_flight = max(self.max_in_flight, sum(b is not None for b in self.busy))
+
+    def tick(self) -> None:
+        """Reap finished micro-batches, then launch new ones on free streams."""
+        self._reap()
+        for k in range(len(self.busy)):
+            if self.busy[k] is None and self.waiting:
+                self._launch(k)
+
+    def drain(self, timeout_s: float = 120.0) -> None:
+        end = time.perf_counter() + timeout_s
+        while not self.idle:
+            if time.perf_counter() > end:
+                raise TimeoutError("server did not drain")
+            self.tick()
+
+
+def poisson_arrivals(count: int, qps: float, seed: int = 0) -> np.ndarray:
+    """Arrival times (s) of a Poisson process of rate qps."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / qps, size=count))
+
+
+def run_load(server: Server, graphs: list, eps_choices, qps: float, count: int,
+             seed: int = 0) -> list[Request]:
+    """Offer `count` requests at Poisson rate `qps`; request i peels
+    graphs[i % len(graphs)] with an eps drawn from eps_choices.  Returns the
+    completed requests (arrival, admission, completion times in seconds)."""
+    rng = np.random.default_rng(seed + 1)
+    arrivals = poisson_arrivals(count, qps, seed)
+    pick = rng.integers(0, len(eps_choices), size=count)
+    reqs = [Request(i, graphs[i % len(graphs)], tuple(eps_choices[pick[i]]), float(arrivals[i]))
+            for i in range(count)]
+    server.t0 = time.perf_counter()
+    nxt = 0
+    while nxt < count or not server.idle:
+        now = server.now()
+        while nxt < count and reqs[nxt].arrival <= now:
+            server.submit(reqs[nxt])
+            nxt += 1
+        server.tick()
+    return reqs
+
+
+def latency_stats(reqs: list[Request]) -> dict:
+    lat = np.array([r.done - r.arrival for r in reqs]) * 1e3
+    queue = np.array([r.admitted - r.arrival for r in reqs]) * 1e3
+    span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
+    return {"requests": len(reqs), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_ms": round(float(lat.mean()), 3),
+            "queue_p50_ms": round(float(np.percentile(queue, 50)), 3),
+            "graphs_per_s": round(len(reqs) / span, 1)}
