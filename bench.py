@@ -23,6 +23,8 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+
+import numpy as np
 import json
 import os
 import statistics
@@ -94,6 +96,11 @@ def main() -> int:
                     help="skip the batched (4096-graph) measurement")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving (Poisson request stream) measurement")
+    ap.add_argument("--serve-qps", type=float, default=2000.0)
+    ap.add_argument("--serve-requests", type=int, default=3000)
+    ap.add_argument("--serve-pool", type=int, default=256)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES bytes device-to-device once (reference kernel for "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE scaling) and exit")
@@ -212,6 +219,9 @@ def main() -> int:
     batch = None
     if not args.no_batch:
         batch = bench_batch(args, torch, dsg, num, den, run_oracle=not args.no_cpu_baseline)
+    serving = None
+    if not args.no_serve:
+        serving = bench_serve(args, torch)
 
     line = {
         "metric": METRIC,
@@ -245,9 +255,11 @@ def main() -> int:
         "cpu_baseline": cpu,
         "parity": parity,
         "batch": batch,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
     ok = parity in (None, "exact") and (batch is None or batch["parity"] in (None, "exact"))
+    ok = ok and (serving is None or serving["parity"] == "exact")
     return 0 if ok else 3
 
 
@@ -358,6 +370,65 @@ def bench_batch(args, torch, dsg, num: int, den: int, run_oracle: bool) -> dict:
         "cpu_baseline": cpu,
         "parity": parity,
     }
+
+
+
+def bench_serve(args, torch) -> dict:
+    """Latency and throughput of the serving loop under a Poisson request
+    stream; every served result is checked against the same graph peeled
+    alone by the single-graph path."""
+    from paper_2103_00154_amd import dsg, inputs, serve
+    eps_choices = ((1, 100), (1, 10), (1, 2))
+    t0 = time.time()
+    specs = inputs.serving_specs(args.serve_pool, seed=0)
+    b = inputs.make_batch(specs)
+    graphs = [b.graph(i) for i in range(b.count)]
+    hg = [serve.HostGraph.from_graph(g) for g in graphs]
+    log(f"serve: pool of {len(graphs)} graphs (n median {int(np.median(b.n))}, max "
+        f"{int(b.n.max())}; m total {int(b.m.sum())}) built in {time.time() - t0:.1f}s")
+    budget = 16 << 30
+    srv = serve.Server(budget, streams=4, max_batch=256)
+    # warm-up: a short stream, not timed
+    serve.run_load(srv, hg, eps_choices, qps=args.serve_qps, count=64, seed=99)
+    srv.close()
+    del srv
+    srv = serve.Server(budget, streams=4, max_batch=256)
+    reqs = serve.run_load(srv, hg, eps_choices, qps=args.serve_qps, count=args.serve_requests,
+                          seed=7)
+    srv.close()
+    torch.cuda.synchronize()
+    st = serve.latency_stats(reqs)
+    log(f"serve: {st}; {srv.batches} micro-batches (mean {np.mean(srv.batch_sizes):.1f} "
+        f"requests), up to {srv.max_in_flight} in flight, {srv.big_done} requests above "
+        f"{srv.big_vertices} vertices in the single-graph lane, arena peak "
+        f"{srv.arena.peak >> 20} MiB")
+    # every (graph, eps) pair that was served, peeled alone
+    same = all(r.result["status"] == 0 for r in reqs)
+    seen = {}
+    for r in reqs:
+        seen.setdefault((r.rid % len(graphs), r.eps), []).append(r)
+    for (gi, e), rs in seen.items():
+        g = graphs[gi]
+        rp = torch.from_numpy(g.row_ptr).cuda()
+        ci = torch.from_numpy(g.col_idx if g.m else np.zeros(1, np.int32)).cuda()
+        a = dsg.peel(rp, ci, e, m=g.m)
+        ab = a.best.cpu().numpy()
+        for r in rs:
+            same = same and (r.result["num"], r.result["den"], r.result["passes"],
+                             r.result["best_pass"]) == (a.num, a.den, a.passes, a.best_pass)
+            same = same and np.array_equal(r.best, ab)
+    parity = "exact" if same else "MISMATCH"
+    log(f"serve: results vs peeled alone: {parity} ({len(seen)} graph/eps pairs)")
+    return dict(st, **{
+        "workload": (f"Poisson stream at {args.serve_qps:g} requests/s of Chung-Lu graphs, n "
+                     f"lognormal (median 20000, sigma 1, capped at 2000000), avg degree U[8, 64], "
+                     f"gamma U[2.1, 2.8], eps from {{1/100, 1/10, 1/2}}; pool of "
+                     f"{len(graphs)} graphs, each request uploads its CSR"),
+        "offered_qps": args.serve_qps, "budget_bytes": budget, "streams": 4,
+        "micro_batches": srv.batches, "mean_batch": round(float(np.mean(srv.batch_sizes)), 2),
+        "max_in_flight": srv.max_in_flight, "arena_peak_bytes": srv.arena.peak,
+        "single_graph_lane": {"above_vertices": srv.big_vertices, "requests": srv.big_done},
+        "parity": parity})
 
 
 if __name__ == "__main__":

@@ -12,13 +12,20 @@ as soon as a stream and memory are free, so their work overlaps on the device
 with the batches already running (continuous batching).  Completed batches
 free their memory, and their results are read back.
 
+Graphs with more vertices than a workgroup keeps in LDS would hold one CU
+for a long time (their state spills to device memory), so they take a
+separate lane instead: worker threads peel them one at a time with the
+multi-kernel single-graph path (dsg_peel_ex), which spreads one graph over
+the whole device, on streams of their own, concurrently with the batches.
+
 Every result is exactly the result of peeling the graph alone: the kernels
-are exact integer code and a graph is peeled by one workgroup, independently
-of what else shares the launch.
+are exact integer code, and in a batch a graph is peeled by one workgroup,
+independently of what else shares the launch.
 """
 from __future__ import annotations
 
 import bisect
+import threading
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -122,14 +129,36 @@ def footprint(n: int, m: int) -> int:
 
 
 class Server:
-    """Continuous-batching peel server on one device (see the module doc)."""
+    """Continuous-batching peel server on one device (see the module doc).
+
+    ``big_vertices``: requests with more vertices go to the single-graph lane
+    (None: the LDS vertex capacity of the batch kernel's launch shape; 0 or a
+    huge value disables the lane); ``big_lanes`` worker threads serve it."""
 
     def __init__(self, budget_bytes: int, *, streams: int = 4, max_batch: int = 512,
-                 launch: dict | None = None, device=None):
+                 launch: dict | None = None, device=None, big_vertices: int | None = None,
+                 big_lanes: int = 1):
         import torch
         self.device = torch.device(device or "cuda")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         self.buf = torch.empty(budget_bytes, dtype=torch.uint8, device=self.device)
         self.arena = Arena(budget_bytes)
+        self.lock = threading.Lock()
+        if big_vertices is None:
+            big_vertices = _lds_vertices(launch, self.device)
+        self.big_vertices = big_vertices
+        self.big_waiting: deque[Request] = deque()
+        self.big_busy = 0
+        self.big_done = 0
+        self._stop = False
+        self.error: BaseException | None = None
+        self._cv = threading.Condition(self.lock)
+        self._lanes = []
+        for _ in range(big_lanes if big_vertices else 0):
+            th = threading.Thread(target=self._big_lane, daemon=True)
+            th.start()
+            self._lanes.append(th)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self.busy = [None] * streams
         self.waiting: deque[Request] = deque()
@@ -145,13 +174,89 @@ class Server:
         return time.perf_counter() - self.t0
 
     def submit(self, req: Request) -> None:
-        if footprint(req.graph.n, req.graph.m) > self.arena.size:
+        big = bool(self.big_vertices) and req.graph.n > self.big_vertices
+        need = (_single_footprint(req.graph.n, req.graph.m) if big
+                else footprint(req.graph.n, req.graph.m))
+        if need > self.arena.size:
             raise ValueError(f"request {req.rid} needs more memory than the whole budget")
-        self.waiting.append(req)
+        if big:
+            with self._cv:
+                self.big_waiting.append(req)
+                self._cv.notify()
+        else:
+            self.waiting.append(req)
 
     @property
     def idle(self) -> bool:
-        return not self.waiting and all(b is None for b in self.busy)
+        with self.lock:
+            big_idle = not self.big_waiting and self.big_busy == 0
+        return big_idle and not self.waiting and all(b is None for b in self.busy)
+
+    def close(self) -> None:
+        with self._cv:
+            self._stop = True
+            self._cv.notify_all()
+        for th in self._lanes:
+            th.join()
+
+    def _big_lane(self) -> None:
+        try:
+            self._big_lane_loop()
+        except BaseException as exc:  # surfaced by tick() in the serving thread
+            with self._cv:
+                self.error = exc
+
+    def _big_lane_loop(self) -> None:
+        """Worker: peel large requests one at a time with the single-graph
+        path, each with its own arena region, on a stream of its own."""
+        import torch
+        torch.cuda.set_device(self.device)
+        stream = torch.cuda.Stream(device=self.device)
+        while True:
+            with self._cv:
+                while not self._stop and not self.big_waiting:
+                    self._cv.wait()
+                if self._stop:
+                    return
+                rq = self.big_waiting[0]
+                g = rq.graph
+                nb_csr = 4 * (g.n + 1 + 2 * g.m)
+                nb_ws = dsg.workspace_bytes(g.n, g.m)
+                got = self._try_place((nb_csr, 4 * max(g.n, 1), nb_ws))
+                if got is None:
+                    self._cv.wait(0.0005)   # memory frees up as batches finish
+                    continue
+                self.big_waiting.popleft()
+                self.big_busy += 1
+            rq.admitted = self.now()
+            (o_csr, _), (o_best, _), (o_ws, _) = got
+            ints = self.buf.view(torch.int32)
+            try:
+                with torch.cuda.stream(stream):
+                    dev = ints[o_csr // 4:o_csr // 4 + g.csr.numel()]
+                    dev.copy_(g.csr, non_blocking=True)
+                    best = ints[o_best // 4:o_best // 4 + max(g.n, 1)]
+                    r = dsg.peel(dev[:g.n + 1], dev[g.n + 1:] if g.m else dev[:1], rq.eps,
+                                 m=g.m, best_ids=best, workspace=self.buf[o_ws:o_ws + nb_ws],
+                                 stream=stream)
+                    b = r.best.cpu().numpy()
+                rq.result = {"num": r.num, "den": r.den, "passes": r.passes,
+                             "best_pass": r.best_pass, "best_size": len(b), "status": 0}
+                rq.best = b
+            except BaseException as exc:  # surfaced by tick() in the serving thread
+                status = exc.status if isinstance(exc, dsg.DsgError) else dsg.DSG_EINTERNAL
+                rq.result = {"num": 0, "den": 0, "passes": 0, "best_pass": 0, "best_size": 0,
+                             "status": status}
+                rq.best = np.zeros(0, dtype=np.int32)
+                with self._cv:
+                    self.error = exc
+            rq.done = self.now()
+            with self._cv:
+                for off, nb in got:
+                    self.arena.free(off, nb)
+                self.completed.append(rq)
+                self.big_busy -= 1
+                self.big_done += 1
 
     # ------------------------------------------------------------------
     def _reap(self) -> None:
@@ -166,9 +271,10 @@ class Server:
                 rq.result = results[i]
                 a = mb.best_off[i]
                 rq.best = best[a:a + rq.result["best_size"]].copy()
-                self.completed.append(rq)
-            for off, nb in mb.allocs:
-                self.arena.free(off, nb)
+            with self.lock:
+                for off, nb in mb.allocs:
+                    self.arena.free(off, nb)
+                self.completed.extend(mb.reqs)
             self.busy[k] = None
 
     def _shared_bytes(self, take) -> tuple[int, int]:
@@ -188,6 +294,10 @@ class Server:
         return got
 
     def _launch(self, k: int) -> None:
+        with self.lock:
+            self._launch_locked(k)
+
+    def _launch_locked(self, k: int) -> None:
         import torch
         take, allocs = [], []
         # admit in arrival order while the request's CSR and the batch's
@@ -250,6 +360,8 @@ class Server:
 
     def tick(self) -> None:
         """Reap finished micro-batches, then launch new ones on free streams."""
+        if self.error is not None:
+            raise RuntimeError("single-graph lane failed") from self.error
         self._reap()
         for k in range(len(self.busy)):
             if self.busy[k] is None and self.waiting:
@@ -263,6 +375,29 @@ class Server:
             self.tick()
 
 
+def _single_footprint(n: int, m: int) -> int:
+    """Arena bytes of a request in the single-graph lane: CSR, output slots
+    and the dsg_peel workspace."""
+    def r(x):
+        return (x + ALIGN - 1) // ALIGN * ALIGN
+    return r(4 * (n + 1 + 2 * m)) + r(4 * max(n, 1)) + r(dsg.workspace_bytes(n, m))
+
+
+_LDS_CACHE: dict = {}
+
+
+def _lds_vertices(launch, device) -> int:
+    """Vertices per graph the batch kernel keeps in LDS for this shape."""
+    key = (str(device), tuple(sorted((launch or {}).items())))
+    if key not in _LDS_CACHE:
+        import torch
+        tab, count = dsg.batch_table([1], [0], [0], [0], [0], (1, 10))
+        ws = torch.empty(dsg.batch_workspace_bytes(1, 0, 1), dtype=torch.uint8, device=device)
+        b = dsg.Batch(tab, count, 2, 0, 1, launch=launch, workspace=ws, device=device)
+        _LDS_CACHE[key] = b.shape["lds_vertices"]
+    return _LDS_CACHE[key]
+
+
 def poisson_arrivals(count: int, qps: float, seed: int = 0) -> np.ndarray:
     """Arrival times (s) of a Poisson process of rate qps."""
     rng = np.random.default_rng(seed)
@@ -270,7 +405,7 @@ def poisson_arrivals(count: int, qps: float, seed: int = 0) -> np.ndarray:
 
 
 def run_load(server: Server, graphs: list, eps_choices, qps: float, count: int,
-             seed: int = 0) -> list[Request]:
+             seed: int = 0, timeout_s: float = 300.0) -> list[Request]:
     """Offer `count` requests at Poisson rate `qps`; request i peels
     graphs[i % len(graphs)] with an eps drawn from eps_choices.  Returns the
     completed requests (arrival, admission, completion times in seconds)."""
@@ -282,6 +417,8 @@ def run_load(server: Server, graphs: list, eps_choices, qps: float, count: int,
     server.t0 = time.perf_counter()
     nxt = 0
     while nxt < count or not server.idle:
+        if server.now() > arrivals[-1] + timeout_s:
+            raise TimeoutError(f"{count - len(server.completed)} requests still open")
         now = server.now()
         while nxt < count and reqs[nxt].arrival <= now:
             server.submit(reqs[nxt])

@@ -59,6 +59,7 @@ def test_continuous_batching_matches_alone_results():
     budget = 6 * max(serve.footprint(g.n, g.m) for g in graphs)
     srv = serve.Server(budget, streams=4, max_batch=32)
     reqs = serve.run_load(srv, hg, EPS, qps=20_000, count=300, seed=2)
+    srv.close()
     torch.cuda.synchronize()
     st = serve.latency_stats(reqs)
     say(f"stats {st}; batches {srv.batches}, max batch {max(srv.batch_sizes)}, "
@@ -84,11 +85,18 @@ def test_same_results_alone_and_in_a_mix_of_sizes():
     graphs += [inputs.chung_lu(150_000, 24, 2.3, seed=77), inputs.erdos_renyi(90_000, 500_000, 78)]
     alone = _alone(graphs)
     hg = [serve.HostGraph.from_graph(g) for g in graphs]
-    srv = serve.Server(1 << 30, streams=3, max_batch=8)
-    reqs = serve.run_load(srv, hg, EPS, qps=5_000, count=96, seed=5)
-    torch.cuda.synchronize()
-    say(f"stats {serve.latency_stats(reqs)}; batches {srv.batches}")
-    _check(reqs, graphs, alone)
+    for lane in (True, False):
+        # with the single-graph lane for the large graphs, and without it
+        srv = serve.Server(1 << 30, streams=3, max_batch=8,
+                           big_vertices=None if lane else 0)
+        reqs = serve.run_load(srv, hg, EPS, qps=5_000, count=96, seed=5)
+        srv.close()
+        torch.cuda.synchronize()
+        say(f"lane {lane}: stats {serve.latency_stats(reqs)}; batches {srv.batches}, "
+            f"large-graph lane {srv.big_done}")
+        assert (srv.big_done > 0) == lane
+        assert srv.arena.used == 0
+        _check(reqs, graphs, alone)
 
 
 def test_request_larger_than_the_budget_is_refused():
