@@ -92,10 +92,15 @@ def main() -> int:
     ap.add_argument("--eps", default="1/10")
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="single,batch,serve",
+                    help="comma list of measurements to run: single (the headline "
+                         "single-graph peel), batch, serve; profiler runs pick one")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched (4096-graph) measurement")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--batch-shape", default="",
+                    help="BLOCK,WALK_ITEMS,BLOCKS_PER_CU instead of autotuning")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the serving (Poisson request stream) measurement")
     ap.add_argument("--serve-qps", type=float, default=2000.0)
@@ -129,6 +134,23 @@ def main() -> int:
         print("bench.py needs a HIP device", file=sys.stderr)
         return 1
     from paper_2103_00154_amd import dsg
+
+    legs = set(args.legs.split(","))
+    if args.no_batch:
+        legs.discard("batch")
+    if args.no_serve:
+        legs.discard("serve")
+    if "single" not in legs:
+        # profiler runs of one leg: the JSON line carries only that leg
+        torch.cuda.set_device(0)
+        line = {"metric": METRIC, "value": None, "unit": "GTEPS", "n_gpus": 1,
+                "steps": args.steps, "warmup": args.warmup, "legs": sorted(legs),
+                "batch": bench_batch(args, torch, dsg, num, den,
+                                     run_oracle=not args.no_cpu_baseline)
+                if "batch" in legs else None,
+                "serving": bench_serve(args, torch) if "serve" in legs else None}
+        print(json.dumps(line), flush=True)
+        return 0
 
     t0 = time.time()
     g, desc = make_workload(args.workload)
@@ -217,10 +239,10 @@ def main() -> int:
         log(f"oracle: {t_cpu:.2f} s ({g.m / t_cpu / 1e9:.3f} GTEPS), parity {parity}")
 
     batch = None
-    if not args.no_batch:
+    if "batch" in legs:
         batch = bench_batch(args, torch, dsg, num, den, run_oracle=not args.no_cpu_baseline)
     serving = None
-    if not args.no_serve:
+    if "serve" in legs:
         serving = bench_serve(args, torch)
 
     line = {
@@ -279,8 +301,12 @@ def bench_batch(args, torch, dsg, num: int, den: int, run_oracle: bool) -> dict:
     tab, _ = dsg.batch_table(b.n, b.m, b.rp_off, b.ci_off, b.out_off, (num, den))
     torch.cuda.synchronize()
 
-    shape, timings = autotune.tune_batch(tab, count, len(b.row_ptr), e_tot, out_len, rp, ci,
-                                         log=log)
+    if args.batch_shape:
+        blk, it, bpc = (int(x) for x in args.batch_shape.split(","))
+        shape, timings = {"block": blk, "walk_items": it, "blocks_per_cu": bpc}, []
+    else:
+        shape, timings = autotune.tune_batch(tab, count, len(b.row_ptr), e_tot, out_len, rp, ci,
+                                             log=log)
     log(f"batch: autotuned shape {shape}")
     plan = dsg.Batch(tab, count, len(b.row_ptr), e_tot, out_len, launch=shape)
     best = torch.empty(max(out_len, 1), dtype=torch.int32, device=dev)
