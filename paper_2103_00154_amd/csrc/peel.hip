@@ -214,11 +214,26 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
         }
         int32_t ll[kMarkItems];
 #pragma unroll
-        for (int j = 0; j < kMarkItems; ++j) {
-            const bool ok = (uint64_t)(int64_t)vv[j] < (uint64_t)n;
-            if (!ok) vv[j] = -1;
-            // row length of a failure with degree > 0 (pass 1: the degree itself)
-            ll[j] = (!lin || !ok || dd[j] > T || dd[j] <= 0) ? dd[j] : rp[vv[j] + 1] - rp[vv[j]];
+        for (int j = 0; j < kMarkItems; ++j)
+            if ((uint64_t)(int64_t)vv[j] >= (uint64_t)n) vv[j] = -1;
+        if (!lin) {
+#pragma unroll
+            for (int j = 0; j < kMarkItems; ++j) ll[j] = dd[j];
+        } else {
+            // row length of a failure with degree > 0 (pass 1: the degree
+            // itself); all row bounds are loaded before any is used (row 0
+            // stands in for the other entries)
+            int32_t rs[kMarkItems], re[kMarkItems];
+            bool need[kMarkItems];
+#pragma unroll
+            for (int j = 0; j < kMarkItems; ++j) {
+                need[j] = vv[j] >= 0 && dd[j] <= T && dd[j] > 0;
+                const int32_t x = need[j] ? vv[j] : 0;
+                rs[j] = rp[x];
+                re[j] = rp[x + 1];
+            }
+#pragma unroll
+            for (int j = 0; j < kMarkItems; ++j) ll[j] = need[j] ? re[j] - rs[j] : dd[j];
         }
         // 2. decisions, removal passes and live bits
         uint32_t cA = 0, cL = 0, cE = 0, cDr = 0, cDs = 0;
@@ -392,11 +407,21 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
         } else {
             load8(lin, base, S, -1, vv);
             load8(din, base, S, 0, dd);
+            // row bounds of the failures with degree > 0, all loaded before
+            // any is used (row 0 stands in for the other entries)
+            int32_t re[kMarkItems];
+            bool need[kMarkItems];
 #pragma unroll
             for (int j = 0; j < kMarkItems; ++j) {
-                const bool need = (uint64_t)(int64_t)vv[j] < (uint64_t)n && dd[j] <= T && dd[j] > 0;
-                rs[j] = need ? rp[vv[j]] : 0;
-                ll[j] = need ? rp[vv[j] + 1] - rs[j] : 0;
+                need[j] = (uint64_t)(int64_t)vv[j] < (uint64_t)n && dd[j] <= T && dd[j] > 0;
+                const int32_t x = need[j] ? vv[j] : 0;
+                rs[j] = rp[x];
+                re[j] = rp[x + 1];
+            }
+#pragma unroll
+            for (int j = 0; j < kMarkItems; ++j) {
+                ll[j] = need[j] ? re[j] - rs[j] : 0;
+                if (!need[j]) rs[j] = 0;
             }
         }
         uint32_t cA = 0, cL = 0, cE = 0, cDs = 0;
