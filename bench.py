@@ -92,7 +92,7 @@ def main() -> int:
     ap.add_argument("--eps", default="1/10")
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="single,batch,serve",
+    ap.add_argument("--legs", default="single,batch,serve,sweep",
                     help="comma list of measurements to run: single (the headline "
                          "single-graph peel), batch, serve; profiler runs pick one")
     ap.add_argument("--no-batch", action="store_true",
@@ -148,7 +148,9 @@ def main() -> int:
                 "batch": bench_batch(args, torch, dsg, num, den,
                                      run_oracle=not args.no_cpu_baseline)
                 if "batch" in legs else None,
-                "serving": bench_serve(args, torch) if "serve" in legs else None}
+                "serving": bench_serve(args, torch) if "serve" in legs else None,
+                "eps_sweep": bench_sweep(args, torch, run_oracle=not args.no_cpu_baseline)
+                if "sweep" in legs else None}
         print(json.dumps(line), flush=True)
         return 0
 
@@ -244,6 +246,9 @@ def main() -> int:
     serving = None
     if "serve" in legs:
         serving = bench_serve(args, torch)
+    eps_sweep = None
+    if "sweep" in legs:
+        eps_sweep = bench_sweep(args, torch, run_oracle=not args.no_cpu_baseline)
 
     line = {
         "metric": METRIC,
@@ -278,10 +283,12 @@ def main() -> int:
         "parity": parity,
         "batch": batch,
         "serving": serving,
+        "eps_sweep": eps_sweep,
     }
     print(json.dumps(line), flush=True)
     ok = parity in (None, "exact") and (batch is None or batch["parity"] in (None, "exact"))
     ok = ok and (serving is None or serving["parity"] == "exact")
+    ok = ok and (eps_sweep is None or eps_sweep["parity"] in (None, "exact"))
     return 0 if ok else 3
 
 
@@ -455,6 +462,40 @@ def bench_serve(args, torch) -> dict:
         "max_in_flight": srv.max_in_flight, "arena_peak_bytes": srv.arena.peak,
         "single_graph_lane": {"above_vertices": srv.big_vertices, "requests": srv.big_done},
         "parity": parity})
+
+
+def bench_sweep(args, torch, run_oracle: bool) -> dict:
+    """The peel of R-MAT scale 20 at eps from 0 to 5: passes, density, time
+    per eps, each against the oracle (parity and the oracle's time)."""
+    from paper_2103_00154_amd import inputs, sweep
+    eps_list = ((0, 1), (1, 100), (1, 20), (1, 10), (1, 2), (1, 1), (2, 1), (5, 1))
+    g = inputs.rmat(20, 16, seed=0)
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    ci = torch.from_numpy(g.col_idx).cuda()
+    pts = sweep.eps_sweep(rp, ci, eps_list, reps=5)
+    rows = []
+    same = True
+    for pt in pts:
+        row = {"eps": f"{pt.eps[0]}/{pt.eps[1]}", "passes": pt.passes, "best_pass": pt.best_pass,
+               "dens_num": pt.num, "dens_den": pt.den, "density": round(pt.density, 3),
+               "ms": round(pt.ms, 4), "gteps": round(g.m / (pt.ms * 1e-3) / 1e9, 2),
+               "removed_per_pass": [t["removed"] for t in pt.trace]}
+        if run_oracle:
+            import oracle
+            c0 = time.perf_counter()
+            o = oracle.peel_graph(g, *pt.eps, trace=True)
+            row["oracle_ms"] = round((time.perf_counter() - c0) * 1e3, 1)
+            ok = (pt.passes, pt.best_pass, pt.num, pt.den) == (o.passes, o.best_pass, o.num,
+                                                                o.den)
+            ok = ok and [t["removed"] for t in pt.trace] == [t["removed"] for t in o.trace]
+            same = same and ok
+        rows.append(row)
+        log(f"sweep eps {row['eps']}: passes {pt.passes}, best {pt.num}/{pt.den}, "
+            f"{pt.ms:.3f} ms")
+    return {"workload": "R-MAT scale 20, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 0",
+            "n": g.n, "m": g.m, "points": rows,
+            "parity": ("exact" if same else "MISMATCH") if run_oracle else None,
+            "cpu_baseline_kind": "oracle" if run_oracle else None}
 
 
 if __name__ == "__main__":
