@@ -11,6 +11,10 @@ library and never imports it.
 * :mod:`oracle.exact`     - exact densest-subgraph densities (brute force,
                             Goldberg's max-flow construction) used to check
                             the approximation guarantee.
+* :func:`cbds`            - CBDS-P (Algorithm 2): densest k-core extended by
+                            legitimate vertices (``cbds_oracle.c``).
+* :mod:`oracle.cbds_literal` - the same from the definitions of the k-core and
+                            of the extension step (pure Python, small graphs).
 """
 from __future__ import annotations
 
@@ -51,6 +55,8 @@ def _load():
         lib.dsg_oracle_peel.restype = _I32
         lib.dsg_oracle_check_csr.argtypes = [_P, _P, _I64]
         lib.dsg_oracle_check_csr.restype = _I32
+        lib.dsg_oracle_cbds.argtypes = [_P, _P, _I64, _P, _P, _P]
+        lib.dsg_oracle_cbds.restype = _I32
         _lib = lib
     return _lib
 
@@ -107,3 +113,37 @@ def peel(row_ptr, col_idx, n: int, eps_num: int, eps_den: int, trace: bool = Tru
 
 def peel_graph(g, eps_num: int, eps_den: int, trace: bool = True) -> OracleResult:
     return peel(g.row_ptr, g.col_idx, g.n, eps_num, eps_den, trace=trace)
+
+
+@dataclass
+class CbdsResult:
+    num: int            # |E(S)| of the result S = C_K u L
+    den: int            # |S|
+    core_num: int       # |E(C_K)|
+    core_den: int       # |C_K|
+    K: int              # order of the densest core
+    n_legit: int        # |L|
+    kmax: int           # largest core number
+    best: np.ndarray    # S, ascending int32
+    core: np.ndarray    # core number of every vertex
+    n_eligible: int
+    legit_edges: int    # sum of legits over L plus |E(L)|
+
+
+def cbds(g) -> CbdsResult:
+    """CBDS-P (Section 3.2, Algorithm 2) of a Graph from ``inputs``."""
+    lib = _load()
+    n = g.n
+    core = np.empty(max(n, 1), dtype=np.int32)
+    best = np.empty(max(n, 1), dtype=np.int32)
+    out = np.zeros(10, dtype=np.int64)
+    rp = _arr(g.row_ptr)
+    ci = _arr(g.col_idx if g.col_idx.size else np.zeros(1, np.int32))
+    rc = lib.dsg_oracle_cbds(rp.ctypes.data, ci.ctypes.data, n, core.ctypes.data,
+                             best.ctypes.data, out.ctypes.data)
+    if rc != 0:
+        raise OracleError(rc)
+    o = [int(x) for x in out]
+    return CbdsResult(num=o[0], den=o[1], core_num=o[2], core_den=o[3], K=o[4], n_legit=o[5],
+                      kmax=o[6], best=best[:o[7]].copy(), core=core[:n].copy(), n_eligible=o[8],
+                      legit_edges=o[9])

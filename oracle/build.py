@@ -14,7 +14,7 @@ LIB = HERE / "libdsg_oracle.so"
 def build() -> Path:
     tmp = LIB.with_suffix(".so.tmp")
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
-           str(HERE / "peel_oracle.c"), "-o", str(tmp)]
+           str(HERE / "peel_oracle.c"), str(HERE / "cbds_oracle.c"), "-o", str(tmp)]
     proc = subprocess.run(cmd, capture_output=True, text=True)
     if proc.returncode != 0:
         sys.stderr.write(proc.stdout + proc.stderr)
