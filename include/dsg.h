@@ -183,6 +183,57 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
 int32_t dsg_validate_csr(const dsg_csr* g, int64_t n, int64_t m, int32_t* detail, void* stream);
 
 /* ------------------------------------------------------------------------
+ * CBDS-P (Section 3.2, Algorithm 2): the densest k-core, extended by the
+ * outside vertices that raise its density.
+ *
+ * Phase 1 peels k-core levels: for k = 0, 1, ... every vertex of degree <= k
+ * is removed, repeatedly, until none is left (the PKC level loop); the
+ * remaining graph is then the (k+1)-core, and the next level is the least
+ * degree left.  A vertex removed at level k has core number k.  The densest
+ * core C_K is the non-empty core of greatest density |E|/|V|, the smallest
+ * order K among equal densities (the whole graph, K = 0, included).
+ *
+ * Phase 2: with rho = |E(C_K)| / |C_K|, an outside vertex v is eligible when
+ * its core number exceeds rho, and legitimate when it has more than rho
+ * neighbours in C_K.  All legitimate vertices L join at once: the result is
+ * S = C_K u L, with |E(S)| = |E(C_K)| + (edges from L into C_K) + |E(L)|.
+ * Every comparison is exact (int64 cross-multiplication).
+ * ------------------------------------------------------------------------ */
+
+/* Result of dsg_cbds (host struct). */
+typedef struct {
+    int64_t dens_num;   /* |E(S)| of the result S = C_K u L */
+    int64_t dens_den;   /* |S| */
+    int64_t core_num;   /* |E(C_K)| */
+    int64_t core_den;   /* |C_K| */
+    int32_t core_k;     /* K, the order of the densest core */
+    int32_t kmax;       /* the largest core number */
+    int32_t passes;     /* phase-1 passes (removal rounds and level ends) */
+    int32_t reserved;
+    int64_t n_eligible; /* outside vertices with core number > rho */
+    int64_t n_legit;    /* |L| */
+    int64_t best_size;  /* ids written to best_ids (|S|, or 0 without best_ids) */
+} dsg_cbds_result;
+
+/*
+ * Run CBDS-P on g (CSR as for dsg_peel).
+ *
+ *   best_ids   device, room for n int32, or NULL: S in ascending order.
+ *   core       device, n int32, or NULL: the core number of every vertex.
+ *   out        host; filled on DSG_OK.
+ *   trace      host, trace_cap records, or NULL: one dsg_pass_trace per
+ *              phase-1 pass (thresh is the level k).
+ *   workspace  device, >= dsg_workspace_bytes(n, m) bytes, 256-byte
+ *              aligned; NULL makes the library allocate and free it.
+ *
+ * Errors as for dsg_peel (eps does not apply); the pass watchdog is 2n + 2
+ * phase-1 passes.
+ */
+int32_t dsg_cbds(const dsg_csr* g, int64_t n, int64_t m, int32_t* best_ids, int32_t* core,
+                 dsg_cbds_result* out, dsg_pass_trace* trace, int32_t trace_cap,
+                 void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched peeling: many independent graphs in one persistent launch.
  *
  * Every graph of a batch is peeled exactly as dsg_peel peels it (same

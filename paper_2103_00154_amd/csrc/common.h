@@ -80,6 +80,15 @@ struct alignas(256) DevState {
     int32_t force_bins;   // 1: always use bin regions (launch flag)
     int32_t apply_lanes;  // lanes that share one tile's run in k_apply (4..64)
     int32_t reduce_lanes; // lanes that share one rank in k_reduce (1..16)
+    // k-core levels (CBDS-P phase 1): the threshold is the level k and stays
+    // there while passes remove vertices; a pass that removes none ends the
+    // level, and the next level is the least degree left
+    int32_t core_mode;
+    int32_t min_surv;     // least degree among this pass's survivors
+    uint32_t cb_nelig;    // CBDS-P phase 2: eligible outside vertices
+    uint32_t cb_nlegit;   //   legitimate ones
+    unsigned long long cb_sumlegit;  // their neighbours inside the core
+    unsigned long long cb_el;        // edges among legitimate vertices
 };
 
 struct PassRecord {
@@ -157,6 +166,21 @@ __device__ inline T block_sum(T x, T* red) {
     T all = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) all += red[w];
+    __syncthreads();
+    return all;
+}
+
+// Block-wide minimum of unsigned values, returned to every thread.  Two
+// barriers.
+template <int NW = kWaves>
+__device__ inline uint32_t block_min(uint32_t x, uint32_t* red) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x = min(x, (uint32_t)__shfl_xor(x, off, 64));
+    if (lane_id() == 0) red[wave_id()] = x;
+    __syncthreads();
+    uint32_t all = 0xFFFFFFFFu;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) all = min(all, red[w]);
     __syncthreads();
     return all;
 }

@@ -123,7 +123,8 @@ __device__ inline void load8(const int32_t* __restrict__ p, int64_t base, int64_
 
 __global__ void k_init_state(Work w, const int32_t* __restrict__ rp, int64_t n, int64_t m,
                              int64_t num, int64_t den, int32_t max_pass, int32_t trace_cap,
-                             int32_t part_stride, int32_t max_items, int32_t force_bins) {
+                             int32_t part_stride, int32_t max_items, int32_t force_bins,
+                             int32_t core_mode) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     DevState* st = w.st;
     st->S = n;
@@ -138,8 +139,14 @@ __global__ void k_init_state(Work w, const int32_t* __restrict__ rp, int64_t n, 
     st->tot_walked = st->tot_cross = st->tot_live = st->tot_alist = 0;
     st->chunk = 0;
     st->pass = 1;
-    st->T = pass_threshold(m, n, num, den);
-    st->best_pass = 0;
+    // core levels start at k = 0; the whole graph C_0 is the first candidate
+    // and its cut (core number > cut) is -1
+    st->T = core_mode ? 0 : pass_threshold(m, n, num, den);
+    st->best_pass = core_mode ? -1 : 0;
+    st->core_mode = core_mode;
+    st->min_surv = INT32_MAX;
+    st->cb_nelig = st->cb_nlegit = 0;
+    st->cb_sumlegit = st->cb_el = 0;
     st->done = 0;
     st->status = kStOk;
     st->ticket = 0;
@@ -192,6 +199,9 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
     const int32_t* __restrict__ lin = live_in(w, pass);
     const int32_t* __restrict__ din = deg_in(w, pass);
     const int64_t ntiles = (S + kMarkTile - 1) / kMarkTile;
+    // what removed_at records: the pass, or in core mode the level (which is
+    // the core number of every vertex removed at that level)
+    const int32_t rv = st->core_mode ? T : pass;
     __shared__ uint32_t red[kWaves];
 
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -237,6 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
         }
         // 2. decisions, removal passes and live bits
         uint32_t cA = 0, cL = 0, cE = 0, cDr = 0, cDs = 0;
+        uint32_t dmin = 0xFFFFFFFFu;  // least survivor degree
         uint32_t wi = 0xFFFFFFFFu, wm = 0;
         uint32_t gone8 = 0;  // pass 1: bit j set when entry j fails
 #pragma unroll
@@ -246,7 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
             const int32_t d = dd[j];
             if (d <= T) {
                 if (lin) {
-                    w.removed_at[v] = pass;
+                    w.removed_at[v] = rv;
                     const uint32_t word = (uint32_t)v >> 5;
                     if (word != wi) {
                         if (wm) atomicAnd(&w.dir[wi].x, ~wm);
@@ -265,6 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
             } else {
                 ++cL;
                 cDs += (uint32_t)d;
+                dmin = min(dmin, (uint32_t)d);
             }
         }
         if (lin) {
@@ -277,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
             if (base < S) {
 #pragma unroll
                 for (int j = 0; j < kMarkItems; ++j)
-                    if (base + j < S) w.removed_at[base + j] = (gone8 >> j & 1u) ? pass : kNever;
+                    if (base + j < S) w.removed_at[base + j] = (gone8 >> j & 1u) ? rv : kNever;
             }
             uint32_t gone = gone8 << (8 * (threadIdx.x & 3));
             gone |= __shfl_xor(gone, 1, 64);
@@ -294,9 +306,10 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
         const uint32_t tE = block_sum(cE, red);
         const uint32_t tDr = block_sum(cDr, red);
         const uint32_t tDs = block_sum(cDs, red);
+        const uint32_t tMin = block_min(dmin, red);
         if (threadIdx.x == 0) {
             w.tiles[2 * t] = make_int4((int)tA, (int)tL, (int)tE, (int)tDr);
-            w.tiles[2 * t + 1] = make_int4((int)tDs, 0, 0, 0);
+            w.tiles[2 * t + 1] = make_int4((int)tDs, (int)tMin, 0, 0);
         }
     }
 }
@@ -320,6 +333,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode,
     const int64_t lo = std::min<int64_t>(nt, per * threadIdx.x);
     const int64_t hi = std::min<int64_t>(nt, lo + per);
     int64_t a = 0, l = 0, e = 0, dr = 0, ds = 0;
+    uint32_t mn = 0xFFFFFFFFu;
 #pragma unroll 8
     for (int64_t i = lo; i < hi; ++i) {
         const int4 c = w.tiles[2 * i];
@@ -327,9 +341,15 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode,
         l += c.y;
         e += (uint32_t)c.z;
         dr += (uint32_t)c.w;
-        if (mode == 0) ds += (uint32_t)w.tiles[2 * i + 1].x;
+        if (mode == 0) {
+            const int4 q = w.tiles[2 * i + 1];
+            ds += (uint32_t)q.x;
+            mn = min(mn, (uint32_t)q.y);
+        }
     }
     __shared__ int64_t red[kScanBlock / 64];
+    __shared__ uint32_t redm[kScanBlock / 64];
+    const uint32_t tmin = block_min<kScanBlock / 64>(mn, redm);
     int64_t ta, tl, te, tds;
     int64_t pa = block_excl_sum<int64_t, kScanBlock / 64>(a, red, &ta);
     int64_t pl = block_excl_sum<int64_t, kScanBlock / 64>(l, red, &tl);
@@ -354,6 +374,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode,
             st->edges = te;
             st->sumdeg = tdr;
             st->sumdeg_surv = tds;
+            st->min_surv = (int32_t)min(tmin, (uint32_t)INT32_MAX);
             st->n_tiles_walk = (int32_t)((te + kWalkTile - 1) / kWalkTile);
             st->nbins = (int32_t)((tl + kBinWidth - 1) >> kBinShift);
             st->walk_mode = (st->nbins <= kNbLds && !st->force_bins) ? 0 : 1;
@@ -521,10 +542,16 @@ __device__ void finish_pass(const Work& w, int32_t* s_flag, int32_t* red) {
             }
             st->tot_walked += S_out > 0 ? st->edges : 0;
             st->tot_cross += cross;
-            if (S_out > 0 && E_out * st->best_S > st->best_E * S_out) {
+            // the best candidate: after every pass, or in core mode after a
+            // pass that removed nothing (the level is done and what is left
+            // is the (T+1)-core; best_pass then holds T, the cut below the
+            // core numbers of the kept vertices)
+            const bool level_end = S_out == S_in;
+            const bool candidate = st->core_mode ? level_end : true;
+            if (candidate && S_out > 0 && E_out * st->best_S > st->best_E * S_out) {
                 st->best_E = E_out;
                 st->best_S = S_out;
-                st->best_pass = pass;
+                st->best_pass = st->core_mode ? st->T : pass;
             }
             st->S = S_out;
             st->E = E_out;
@@ -537,7 +564,10 @@ __device__ void finish_pass(const Work& w, int32_t* s_flag, int32_t* red) {
                 st->done = 1;
                 keep = 0;
             } else {
-                st->T = pass_threshold(E_out, S_out, st->eps_num, st->eps_den);
+                if (!st->core_mode)
+                    st->T = pass_threshold(E_out, S_out, st->eps_num, st->eps_den);
+                else if (level_end)
+                    st->T = st->min_surv;  // the next non-empty level
                 st->pass = pass + 1;
                 st->chunk = std::max<int64_t>(kChunkMin, (cross + kTargetItems - 1) / kTargetItems);
             }
@@ -959,7 +989,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce(Work w) {
 // --------------------------------------------------------------- extract
 // S~ = { v : removed_at[v] > best_pass }, ascending.
 
-__global__ __launch_bounds__(kBlock) void k_extract_count(Work w, int64_t n) {
+// S~ = { v : removed_at[v] > best_pass }, or with `flag` (CBDS-P) also
+// every v with flag[v] != 0.
+__global__ __launch_bounds__(kBlock) void k_extract_count(Work w, int64_t n,
+                                                          const int32_t* __restrict__ flag) {
     const DevState* st = w.st;
     if (!st->done || st->status != kStOk) return;
     const int32_t bp = st->best_pass;
@@ -967,19 +1000,26 @@ __global__ __launch_bounds__(kBlock) void k_extract_count(Work w, int64_t n) {
     __shared__ uint32_t red[kWaves];
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t base = t * kMarkTile + (int64_t)threadIdx.x * kMarkItems;
-        int32_t ra[kMarkItems];
+        int32_t ra[kMarkItems], fl[kMarkItems];
         load8(w.removed_at, base, n, 0, ra);
+        if (flag) {
+            load8(flag, base, n, 0, fl);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kMarkItems; ++j) fl[j] = 0;
+        }
         uint32_t c = 0;
 #pragma unroll
         for (int j = 0; j < kMarkItems; ++j)
-            if (base + j < n && ra[j] > bp) ++c;
+            if (base + j < n && (ra[j] > bp || fl[j])) ++c;
         const uint32_t tc = block_sum(c, red);
         if (threadIdx.x == 0) w.tiles[2 * t] = make_int4((int)tc, 0, 0, 0);
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_extract_scatter(Work w, int64_t n,
-                                                            int32_t* __restrict__ best) {
+                                                            int32_t* __restrict__ best,
+                                                            const int32_t* __restrict__ flag) {
     const DevState* st = w.st;
     if (!st->done || st->status != kStOk) return;
     const int32_t bp = st->best_pass;
@@ -987,12 +1027,18 @@ __global__ __launch_bounds__(kBlock) void k_extract_scatter(Work w, int64_t n,
     __shared__ uint32_t red[kWaves];
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t base = t * kMarkTile + (int64_t)threadIdx.x * kMarkItems;
-        int32_t ra[kMarkItems];
+        int32_t ra[kMarkItems], fl[kMarkItems];
         load8(w.removed_at, base, n, 0, ra);
+        if (flag) {
+            load8(flag, base, n, 0, fl);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kMarkItems; ++j) fl[j] = 0;
+        }
         uint32_t keep = 0, c = 0;
 #pragma unroll
         for (int j = 0; j < kMarkItems; ++j)
-            if (base + j < n && ra[j] > bp) {
+            if (base + j < n && (ra[j] > bp || fl[j])) {
                 keep |= 1u << j;
                 ++c;
             }
@@ -1002,6 +1048,91 @@ __global__ __launch_bounds__(kBlock) void k_extract_scatter(Work w, int64_t n,
 #pragma unroll
         for (int j = 0; j < kMarkItems; ++j)
             if ((keep >> j & 1u) && pos < n) best[pos++] = (int32_t)(base + j);
+    }
+}
+
+// ================================================================ CBDS-P
+// Phase 2 of Algorithm 2 (Section 3.2), after the k-core levels.  removed_at
+// holds every vertex's core number; the densest core is C_K = { v : core(v)
+// > cut } with cut = K - 1 = best_pass, |E(C_K)| = best_E, |C_K| = best_S,
+// and rho = best_E / best_S.  All tests are exact cross-multiplications.
+
+// Outside vertices with core(v) > rho (the only ones that can have more
+// than rho neighbours in C_K, since a vertex's neighbours inside a core it
+// is not part of number at most its core number) go to `elist`.  Also
+// clears the legitimate flags.
+__global__ __launch_bounds__(kBlock) void k_cbds_eligible(Work w, int64_t n, int32_t* flag,
+                                                          int32_t* elist) {
+    DevState* st = w.st;
+    if (!st->done || st->status != kStOk) return;
+    const int32_t cut = st->best_pass;
+    const int64_t me = st->best_E, mv = st->best_S;
+    for (int64_t b = (int64_t)blockIdx.x * kBlock; b < n; b += (int64_t)gridDim.x * kBlock) {
+        const int64_t v = b + threadIdx.x;
+        bool elig = false;
+        if (v < n) {
+            flag[v] = 0;
+            const int32_t c = w.removed_at[v];
+            elig = c <= cut && (int64_t)c * mv > me;
+        }
+        // one atomic per wave
+        const unsigned long long mask = __ballot(elig);
+        if (mask) {
+            uint32_t at = 0;
+            if (lane_id() == 0) at = atomicAdd(&st->cb_nelig, (uint32_t)__popcll(mask));
+            at = __shfl(at, 0, 64);
+            if (elig) elist[at + lanes_below(mask)] = (int32_t)v;
+        }
+    }
+}
+
+// legits(v) = neighbours of v inside C_K, one wave per eligible vertex;
+// v is legitimate when legits(v) > rho.
+__global__ __launch_bounds__(kBlock) void k_cbds_legits(Work w, const int32_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ ci, int64_t n,
+                                                        int32_t* flag, const int32_t* elist,
+                                                        int32_t* llist) {
+    DevState* st = w.st;
+    if (!st->done || st->status != kStOk) return;
+    const int32_t cut = st->best_pass;
+    const int64_t me = st->best_E, mv = st->best_S;
+    const int64_t ne = st->cb_nelig;
+    const int64_t waves = (int64_t)gridDim.x * kWaves;
+    for (int64_t i = (int64_t)blockIdx.x * kWaves + wave_id(); i < ne; i += waves) {
+        const int32_t v = elist[i];
+        const int32_t r0 = rp[v], r1 = rp[v + 1];
+        uint32_t cnt = 0;
+        for (int32_t e = r0 + lane_id(); e < r1; e += 64) {
+            const int32_t u = ci[e];
+            cnt += (uint64_t)(int64_t)u < (uint64_t)n && w.removed_at[u] > cut;
+        }
+        cnt = wave_sum(cnt);
+        if (lane_id() == 0 && (int64_t)cnt * mv > me) {
+            flag[v] = 1;
+            atomicAdd(&st->cb_sumlegit, (unsigned long long)cnt);
+            llist[atomicAdd(&st->cb_nlegit, 1u)] = v;
+        }
+    }
+}
+
+// Edges among legitimate vertices, each counted at its smaller end.
+__global__ __launch_bounds__(kBlock) void k_cbds_pairs(Work w, const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci, int64_t n,
+                                                       const int32_t* flag, const int32_t* llist) {
+    DevState* st = w.st;
+    if (!st->done || st->status != kStOk) return;
+    const int64_t nl = st->cb_nlegit;
+    const int64_t waves = (int64_t)gridDim.x * kWaves;
+    for (int64_t i = (int64_t)blockIdx.x * kWaves + wave_id(); i < nl; i += waves) {
+        const int32_t v = llist[i];
+        const int32_t r0 = rp[v], r1 = rp[v + 1];
+        uint32_t cnt = 0;
+        for (int32_t e = r0 + lane_id(); e < r1; e += 64) {
+            const int32_t u = ci[e];
+            cnt += u > v && (uint64_t)(int64_t)u < (uint64_t)n && flag[u] != 0;
+        }
+        cnt = wave_sum(cnt);
+        if (lane_id() == 0 && cnt) atomicAdd(&st->cb_el, (unsigned long long)cnt);
     }
 }
 
@@ -1173,10 +1304,17 @@ size_t dsg_workspace_bytes(int64_t n, int64_t m) {
     return layout(n, m).total;
 }
 
-int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_t eps_den,
-                    int32_t* best_ids, int32_t* removed_at, dsg_result* out,
-                    dsg_pass_trace* trace, int32_t trace_cap, const dsg_launch* launch,
-                    dsg_profile* prof, void* workspace, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// The peel (core_mode 0) or CBDS-P (core_mode 1: k-core levels, then the
+// legitimate-vertex extension, reported in *cb).
+int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_t eps_den,
+                 int32_t core_mode, int32_t* best_ids, int32_t* removed_at, dsg_result* out,
+                 dsg_cbds_result* cb, dsg_pass_trace* trace, int32_t trace_cap,
+                 const dsg_launch* launch, dsg_profile* prof, void* workspace, size_t ws_bytes,
+                 void* stream) {
     if (!out || !g) return DSG_EINVAL;
     int32_t rc = check_sizes(n, m, eps_num, eps_den);
     if (rc != DSG_OK) return rc;
@@ -1191,6 +1329,7 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
         return DSG_EINVAL;
     std::memset(out, 0, sizeof(*out));
     if (prof) std::memset(prof, 0, sizeof(*prof));
+    if (cb) std::memset(cb, 0, sizeof(*cb));
     if (n == 0) return DSG_OK;
 
     hipStream_t s = (hipStream_t)stream;
@@ -1237,7 +1376,10 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
     w.toff = (uint16_t*)(base + L.toff);
     w.trace = (PassRecord*)(base + L.trace);
 
-    max_pass = pass_bound(n, eps_num, eps_den);
+    // core levels: every pass removes a vertex or ends a level, and every
+    // level after the first removes a vertex, so 2n + 1 passes suffice
+    max_pass = core_mode ? (int32_t)std::min<int64_t>(2 * n + 2, INT32_MAX)
+                         : pass_bound(n, eps_num, eps_den);
     {
         const int64_t mt = mark_tiles(n) - 1;
         const int64_t wt = std::max<int64_t>(walk_tiles(m) - 1, 1);
@@ -1259,7 +1401,8 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
     k_init_state<<<1, 64, 0, s>>>(w, g->row_ptr, n, m, eps_num, eps_den, max_pass,
                                   std::min(trace_cap, kTraceCap), (int32_t)part_stride(n),
                                   (int32_t)items_cap,
-                                  launch && (launch->flags & DSG_LAUNCH_BIN_REGIONS) ? 1 : 0);
+                                  launch && (launch->flags & DSG_LAUNCH_BIN_REGIONS) ? 1 : 0,
+                                  core_mode);
     k_init<<<init_grid, kBlock, 0, s>>>(w, g->row_ptr, n);
     DSG_HIP(hipGetLastError());
     DSG_HIP(log.end());
@@ -1284,11 +1427,11 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
             DSG_HIP(log.end());
             ++launched;
         }
-        if (best_ids) {
+        if (best_ids && !core_mode) {
             DSG_HIP(log.begin(kKindExtract));
-            k_extract_count<<<mark_grid, kBlock, 0, s>>>(w, n);
+            k_extract_count<<<mark_grid, kBlock, 0, s>>>(w, n, nullptr);
             k_scan_tiles<<<1, kScanBlock, 0, s>>>(w, 1, n);
-            k_extract_scatter<<<mark_grid, kBlock, 0, s>>>(w, n, best_ids);
+            k_extract_scatter<<<mark_grid, kBlock, 0, s>>>(w, n, best_ids, nullptr);
             DSG_HIP(hipGetLastError());
             DSG_HIP(log.end());
         }
@@ -1301,6 +1444,28 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
         }
         batch = std::min<int32_t>(batch * 2, 64);
     }
+    if (core_mode && t_host_state->status == kStOk) {
+        // CBDS-P phase 2, then S = C_K plus the legitimate vertices; the
+        // live lists and a degree array are free now and hold the flags and
+        // the vertex lists
+        int32_t* flag = w.list0;
+        int32_t* elist = w.list1;
+        int32_t* llist = w.deg0;
+        DSG_HIP(log.begin(kKindExtract));
+        k_cbds_eligible<<<init_grid, kBlock, 0, s>>>(w, n, flag, elist);
+        k_cbds_legits<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, g->col_idx, n, flag, elist,
+                                                   llist);
+        k_cbds_pairs<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, g->col_idx, n, flag, llist);
+        if (best_ids) {
+            k_extract_count<<<mark_grid, kBlock, 0, s>>>(w, n, flag);
+            k_scan_tiles<<<1, kScanBlock, 0, s>>>(w, 1, n);
+            k_extract_scatter<<<mark_grid, kBlock, 0, s>>>(w, n, best_ids, flag);
+        }
+        DSG_HIP(hipGetLastError());
+        DSG_HIP(log.end());
+        DSG_HIP(hipMemcpyAsync(t_host_state, w.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        DSG_HIP(hipStreamSynchronize(s));
+    }
     {
         const DevState& h = *t_host_state;
         if (h.status == kStBadRowPtr) {
@@ -1311,7 +1476,8 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
             rc = DSG_EINTERNAL;
             goto done;
         }
-        if (best_ids && h.best_count != h.best_S) {
+        const int64_t size = core_mode ? h.best_S + (int64_t)h.cb_nlegit : h.best_S;
+        if (best_ids && h.best_count != size) {
             rc = DSG_EINTERNAL;
             goto done;
         }
@@ -1319,7 +1485,19 @@ int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int
         out->dens_den = h.best_S;
         out->passes = h.pass;
         out->best_pass = h.best_pass;
-        out->best_size = h.best_S;
+        out->best_size = size;
+        if (cb) {
+            cb->core_num = h.best_E;
+            cb->core_den = h.best_S;
+            cb->core_k = h.best_pass + 1;
+            cb->kmax = h.T;
+            cb->passes = h.pass;
+            cb->n_eligible = h.cb_nelig;
+            cb->n_legit = h.cb_nlegit;
+            cb->dens_num = h.best_E + (int64_t)h.cb_sumlegit + (int64_t)h.cb_el;
+            cb->dens_den = size;
+            cb->best_size = best_ids ? size : 0;
+        }
         if (trace && trace_cap > 0) {
             const int32_t k = std::min(std::min(trace_cap, kTraceCap), h.pass);
             DSG_HIP(hipMemcpyAsync(trace, w.trace, sizeof(PassRecord) * (size_t)k,
@@ -1356,6 +1534,27 @@ done:
         (void)hipFree(base);
     }
     return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_t eps_den,
+                    int32_t* best_ids, int32_t* removed_at, dsg_result* out,
+                    dsg_pass_trace* trace, int32_t trace_cap, const dsg_launch* launch,
+                    dsg_profile* prof, void* workspace, size_t ws_bytes, void* stream) {
+    return run_peel(g, n, m, eps_num, eps_den, 0, best_ids, removed_at, out, nullptr, trace,
+                    trace_cap, launch, prof, workspace, ws_bytes, stream);
+}
+
+int32_t dsg_cbds(const dsg_csr* g, int64_t n, int64_t m, int32_t* best_ids, int32_t* core,
+                 dsg_cbds_result* out, dsg_pass_trace* trace, int32_t trace_cap,
+                 void* workspace, size_t ws_bytes, void* stream) {
+    if (!out) return DSG_EINVAL;
+    dsg_result r;
+    return run_peel(g, n, m, 0, 1, 1, best_ids, core, &r, out, trace, trace_cap, nullptr,
+                    nullptr, workspace, ws_bytes, stream);
 }
 
 int32_t dsg_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_t eps_den,

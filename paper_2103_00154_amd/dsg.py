@@ -26,7 +26,7 @@ DSG_EINTERNAL = -5
 
 #: every symbol include/dsg.h declares
 EXPORTS = ("dsg_version", "dsg_strerror", "dsg_workspace_bytes", "dsg_peel", "dsg_peel_ex",
-           "dsg_validate_csr", "dsg_batch_workspace_bytes", "dsg_batch_prepare",
+           "dsg_validate_csr", "dsg_cbds", "dsg_batch_workspace_bytes", "dsg_batch_prepare",
            "dsg_batch_run")
 
 TRACE_FIELDS = ("s_in", "e_in", "thresh", "removed", "cross", "intra", "walked", "s_out", "e_out")
@@ -61,6 +61,12 @@ class Profile(ctypes.Structure):
                 ("launches_walk", _I32), ("launches_mark", _I32), ("launches_apply", _I32),
                 ("reserved", _I32), ("walked", _I64), ("cross", _I64),
                 ("live_scanned", _I64), ("walk_list", _I64)]
+
+
+class CbdsResult(ctypes.Structure):
+    _fields_ = [("dens_num", _I64), ("dens_den", _I64), ("core_num", _I64), ("core_den", _I64),
+                ("core_k", _I32), ("kmax", _I32), ("passes", _I32), ("reserved", _I32),
+                ("n_eligible", _I64), ("n_legit", _I64), ("best_size", _I64)]
 
 
 class BatchGraph(ctypes.Structure):
@@ -121,6 +127,9 @@ def lib():
         h.dsg_peel_ex.restype = _I32
         h.dsg_validate_csr.argtypes = [ctypes.POINTER(CSR), _I64, _I64, ctypes.POINTER(_I32), _P]
         h.dsg_validate_csr.restype = _I32
+        h.dsg_cbds.argtypes = [ctypes.POINTER(CSR), _I64, _I64, _P, _P, ctypes.POINTER(CbdsResult),
+                               _P, _I32, _P, _SZ, _P]
+        h.dsg_cbds.restype = _I32
         h.dsg_batch_workspace_bytes.argtypes = [_I32, _I64, _I64]
         h.dsg_batch_workspace_bytes.restype = _SZ
         h.dsg_batch_prepare.argtypes = [_P, _I32, _I64, _I64, _I64, _P, _P, _SZ, _P,
@@ -250,6 +259,57 @@ def peel(row_ptr, col_idx, eps=(1, 10), *, m: int | None = None, extract: bool =
                       num=res.dens_num, den=res.dens_den, passes=res.passes,
                       best_pass=res.best_pass,
                       removed_at=rem[:n] if rem is not None else None, trace=passes, profile=pd)
+
+
+@dataclass
+class Cbds:
+    best: object        # torch.int32 device tensor: S ascending (None if not extracted)
+    num: int            # |E(S)|
+    den: int            # |S|
+    core_num: int       # |E(C_K)|
+    core_den: int       # |C_K|
+    K: int              # order of the densest core
+    kmax: int
+    passes: int
+    n_eligible: int
+    n_legit: int
+    core: object = None  # torch.int32 device tensor of core numbers, or None
+    trace: list = field(default_factory=list)
+
+
+def cbds(row_ptr, col_idx, *, m: int | None = None, extract: bool = True, core: bool = False,
+         trace: bool = False, workspace=None, stream=None) -> Cbds:
+    """CBDS-P (Section 3.2, Algorithm 2) of the device graph: the densest
+    k-core extended by legitimate vertices (dsg_cbds)."""
+    import torch
+    _check_int32_cuda("row_ptr", row_ptr)
+    _check_int32_cuda("col_idx", col_idx)
+    n = row_ptr.numel() - 1
+    if m is None:
+        m = col_idx.numel() // 2
+    dev = row_ptr.device
+    csr = CSR(row_ptr.data_ptr(), col_idx.data_ptr() if col_idx.numel() else None)
+    best = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if extract else None
+    cores = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if core else None
+    ws_ptr, ws_len = None, 0
+    if workspace is not None:
+        ws_ptr, ws_len = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    cap = min(4096, 2 * n + 2) if trace else 0
+    tr = (PassTrace * max(cap, 1))()
+    res = CbdsResult()
+    with torch.cuda.device(dev):
+        rc = lib().dsg_cbds(ctypes.byref(csr), n, m,
+                            best.data_ptr() if best is not None else None,
+                            cores.data_ptr() if cores is not None else None, ctypes.byref(res),
+                            ctypes.addressof(tr) if cap else None, cap, ws_ptr, ws_len,
+                            _stream_handle(stream))
+    if rc != DSG_OK:
+        raise DsgError(rc, "dsg_cbds")
+    passes = [{f: int(getattr(tr[k], f)) for f in TRACE_FIELDS} for k in range(min(res.passes, cap))]
+    return Cbds(best=best[:res.best_size] if best is not None else None, num=res.dens_num,
+                den=res.dens_den, core_num=res.core_num, core_den=res.core_den, K=res.core_k,
+                kmax=res.kmax, passes=res.passes, n_eligible=res.n_eligible,
+                n_legit=res.n_legit, core=cores[:n] if cores is not None else None, trace=passes)
 
 
 def validate_csr(row_ptr, col_idx, m: int | None = None, stream=None) -> int:

@@ -227,3 +227,28 @@ def test_batch_run_rejects_unprepared_plan():
     assert h.dsg_batch_run(ctypes.byref(plan), 0x1000, 0x2000, None, None, 0x3000,
                            None) == dsg.DSG_EINVAL
     assert h.dsg_batch_run(None, 0x1000, 0x2000, None, None, 0x3000, None) == dsg.DSG_EINVAL
+
+
+def test_cbds_struct_and_argument_errors(tmp_path):
+    src = tmp_path / "csizes.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dsg.h"\n'
+                   'int main(void){printf("%zu %zu\\n", sizeof(dsg_cbds_result),'
+                   'offsetof(dsg_cbds_result, n_eligible));return 0;}\n')
+    exe = tmp_path / "csizes"
+    subprocess.run(["gcc", "-std=c11", f"-I{ROOT / 'include'}", str(src), "-o", str(exe)],
+                   check=True)
+    got = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True,
+                                       check=True).stdout.split()))
+    assert got == [ctypes.sizeof(dsg.CbdsResult), dsg.CbdsResult.n_eligible.offset]
+    h = dsg.lib()
+    csr = dsg.CSR(0x1000, 0x2000)
+    res = dsg.CbdsResult()
+    assert h.dsg_cbds(ctypes.byref(csr), 5, 2, None, None, None, None, 0, None, 0,
+                      None) == dsg.DSG_EINVAL
+    assert h.dsg_cbds(ctypes.byref(csr), -1, 2, None, None, ctypes.byref(res), None, 0, None, 0,
+                      None) == dsg.DSG_EINVAL
+    assert h.dsg_cbds(ctypes.byref(csr), 2**31, 2, None, None, ctypes.byref(res), None, 0, None,
+                      0, None) == dsg.DSG_EOVERFLOW
+    assert h.dsg_cbds(ctypes.byref(csr), 0, 0, None, None, ctypes.byref(res), None, 0, None, 0,
+                      None) == dsg.DSG_OK
+    assert (res.dens_num, res.dens_den, res.passes) == (0, 0, 0)
