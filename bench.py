@@ -92,7 +92,7 @@ def main() -> int:
     ap.add_argument("--eps", default="1/10")
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="single,batch,serve,sweep",
+    ap.add_argument("--legs", default="single,batch,serve,sweep,cbds",
                     help="comma list of measurements to run: single (the headline "
                          "single-graph peel), batch, serve; profiler runs pick one")
     ap.add_argument("--no-batch", action="store_true",
@@ -150,7 +150,9 @@ def main() -> int:
                 if "batch" in legs else None,
                 "serving": bench_serve(args, torch) if "serve" in legs else None,
                 "eps_sweep": bench_sweep(args, torch, run_oracle=not args.no_cpu_baseline)
-                if "sweep" in legs else None}
+                if "sweep" in legs else None,
+                "cbds": bench_cbds(args, torch, run_oracle=not args.no_cpu_baseline)
+                if "cbds" in legs else None}
         print(json.dumps(line), flush=True)
         return 0
 
@@ -249,6 +251,9 @@ def main() -> int:
     eps_sweep = None
     if "sweep" in legs:
         eps_sweep = bench_sweep(args, torch, run_oracle=not args.no_cpu_baseline)
+    cbds = None
+    if "cbds" in legs:
+        cbds = bench_cbds(args, torch, run_oracle=not args.no_cpu_baseline)
 
     line = {
         "metric": METRIC,
@@ -284,11 +289,13 @@ def main() -> int:
         "batch": batch,
         "serving": serving,
         "eps_sweep": eps_sweep,
+        "cbds": cbds,
     }
     print(json.dumps(line), flush=True)
     ok = parity in (None, "exact") and (batch is None or batch["parity"] in (None, "exact"))
     ok = ok and (serving is None or serving["parity"] == "exact")
     ok = ok and (eps_sweep is None or eps_sweep["parity"] in (None, "exact"))
+    ok = ok and (cbds is None or all(c["parity"] in (None, "exact") for c in cbds["runs"]))
     return 0 if ok else 3
 
 
@@ -496,6 +503,56 @@ def bench_sweep(args, torch, run_oracle: bool) -> dict:
             "n": g.n, "m": g.m, "points": rows,
             "parity": ("exact" if same else "MISMATCH") if run_oracle else None,
             "cpu_baseline_kind": "oracle" if run_oracle else None}
+
+
+def bench_cbds(args, torch, run_oracle: bool) -> dict:
+    """CBDS-P (Section 3.2, Algorithm 2) on R-MAT scale 20 and on the
+    scale-24 workload: device time, levels and passes, the densest core and
+    the extension, next to the peel's densities at eps = 0 and 1/10 (the
+    comparison the paper's Table 3 makes); parity and time of the oracle."""
+    import statistics as stt
+    from paper_2103_00154_amd import dsg, inputs
+    runs = []
+    for name in ("rmat20", "rmat24"):
+        g = inputs.rmat(20, 16, seed=0) if name == "rmat20" else \
+            inputs.rmat(24, 16, seed=0, planted=(2000, 0.5, 1))
+        rp = torch.from_numpy(g.row_ptr).cuda()
+        ci = torch.from_numpy(g.col_idx).cuda()
+        ws = dsg.alloc_workspace(g.n, g.m)
+        r = dsg.cbds(rp, ci, workspace=ws)
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = dsg.cbds(rp, ci, workspace=ws)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        ms = stt.median(times)
+        p0 = dsg.peel(rp, ci, (0, 1), workspace=ws)
+        p1 = dsg.peel(rp, ci, (1, 10), workspace=ws)
+        row = {"workload": name, "n": g.n, "m": g.m, "ms": round(ms, 3),
+               "gteps": round(g.m / (ms * 1e-3) / 1e9, 3), "passes": r.passes, "kmax": r.kmax,
+               "core_k": r.K, "core_density": [r.core_num, r.core_den],
+               "eligible": r.n_eligible, "legit": r.n_legit, "density": [r.num, r.den],
+               "density_value": round(r.num / r.den, 3),
+               "peel_eps0_density": [p0.num, p0.den], "peel_eps_1_10_density": [p1.num, p1.den]}
+        if run_oracle:
+            import oracle
+            c0 = time.perf_counter()
+            o = oracle.cbds(g)
+            row["oracle_ms"] = round((time.perf_counter() - c0) * 1e3, 1)
+            same = (r.num, r.den, r.core_num, r.core_den, r.K, r.n_legit, r.kmax) == (
+                o.num, o.den, o.core_num, o.core_den, o.K, o.n_legit, o.kmax)
+            same = same and np.array_equal(r.best.cpu().numpy(), o.best)
+            row["parity"] = "exact" if same else "MISMATCH"
+        else:
+            row["parity"] = None
+        log(f"cbds {name}: {ms:.3f} ms ({row['gteps']} GTEPS), {r.passes} passes, kmax {r.kmax}, "
+            f"K {r.K}, legit {r.n_legit}, density {r.num}/{r.den} = {r.num / r.den:.3f} "
+            f"(peel eps=0: {p0.num}/{p0.den} = {p0.num / p0.den:.3f}); parity {row['parity']}")
+        runs.append(row)
+        del rp, ci, ws
+    return {"runs": runs}
 
 
 if __name__ == "__main__":
