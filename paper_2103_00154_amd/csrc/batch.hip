@@ -308,16 +308,30 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
             if (nL > 0 && W > 0) {
                 const int32_t ntile = (W + WT - 1) / WT;
                 for (int k = lane; k < WT; k += 64) own[k] = 0;
+                // software pipeline: the row holding a tile's first entry and
+                // the starts of the 256 rows after it are loaded one tile
+                // ahead, while the wave works on the previous tile
+                int32_t rc = wid < ntile ? tf[wid] : 0;
+                int32_t pst[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) pst[k] = apre[min(rc + 1 + 64 * k + lane, nA - 1)];
                 for (int32_t t = wid; t < ntile; t += NW) {
                     const int32_t t0 = t * WT;
                     const int32_t len = min(WT, W - t0);
-                    const int32_t rc = tf[t];
+                    const int32_t tn = t + NW;
+                    const int32_t rcn = tn < ntile ? tf[tn] : 0;
                     // rows that start inside the tile: mark their first
                     // entry (256 rows per step, loads first)
                     for (int32_t r0 = rc + 1; r0 < nA; r0 += 256) {
                         int32_t st[4];
+                        if (r0 == rc + 1) {
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) st[k] = apre[min(r0 + 64 * k + lane, nA - 1)];
+                            for (int k = 0; k < 4; ++k) st[k] = pst[k];
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < 4; ++k)
+                                st[k] = apre[min(r0 + 64 * k + lane, nA - 1)];
+                        }
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
                             const int32_t r = r0 + 64 * k + lane;
@@ -371,6 +385,11 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
                             u[j] = __builtin_nontemporal_load(ci + ab[j] + t0 +
                                                               min(j * 64 + lane, len - 1));
                     }
+                    // next tile's row starts, in flight during this tile's
+                    // state lookups and decrements
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        pst[k] = apre[min(rcn + 1 + 64 * k + lane, nA - 1)];
                     // states: the LDS word for ids below cap, the removal
                     // pass (device memory) above
                     uint32_t sv[IT];
@@ -418,6 +437,7 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
                             ++intra;
                         }
                     }
+                    rc = rcn;
                 }
             }
             if (dev_state) __threadfence();
