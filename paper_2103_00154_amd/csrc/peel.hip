@@ -1443,6 +1443,19 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
             goto done;
         }
         batch = std::min<int32_t>(batch * 2, 64);
+        if (core_mode && !(launch && (launch->mark_grid || launch->walk_grid))) {
+            // k-core levels run many light passes; every kernel loops over
+            // its tiles with a grid stride, and the live set only shrinks,
+            // so grids sized for the live set seen now stay correct and
+            // dispatch far fewer idle workgroups
+            const int64_t S = std::max<int64_t>(t_host_state->S, 1);
+            const int64_t cap = (int64_t)di.cus * 8;
+            mark_grid = (unsigned)std::max<int64_t>(1, std::min(cap, mark_tiles(S) - 1));
+            walk_grid = (unsigned)std::max<int64_t>(
+                1, std::min<int64_t>((int64_t)di.cus * di.walk_blocks_per_cu,
+                                     std::max<int64_t>(mark_grid, di.cus)));
+            reduce_grid = (unsigned)std::max<int64_t>(1, std::min(cap, (S * 16 + kBlock - 1) / kBlock));
+        }
     }
     if (core_mode && t_host_state->status == kStOk) {
         // CBDS-P phase 2, then S = C_K plus the legitimate vertices; the
