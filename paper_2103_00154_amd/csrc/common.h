@@ -13,7 +13,8 @@ constexpr int kMarkItems = 8;                    // live-list entries per thread
 constexpr int kMarkTile = kBlock * kMarkItems;   // live-list entries per tile
 constexpr int kWalkItems = 16;                   // adjacency entries per thread
 constexpr int kWalkTile = kBlock * kWalkItems;   // adjacency entries per tile
-static_assert(kWalkItems % 4 == 0, "the owner scan moves int4 words");
+static_assert(kWalkItems % 8 == 0, "the owner scan moves 16-byte words of 16-bit entries");
+static_assert(kWalkTile < 65536, "owner indices are 16-bit");
 constexpr int kTraceCap = 4096;                  // device trace records
 constexpr int32_t kNever = INT32_MAX;            // removed_at of a vertex still present
 
@@ -30,6 +31,19 @@ constexpr int kApplyBlock = 1024;                // threads of an apply workgrou
 constexpr int kApplyBatch = 8;                   // record loads per lane before counting
 constexpr int64_t kChunkMin = 8192;              // least records per apply work item
 constexpr int64_t kTargetItems = 512;            // apply work items aimed for per pass
+
+// Survivor filter of the walk: when a pass leaves at most kFiltBits
+// survivors, a bitmap with the bit of hash(id) set for every survivor is
+// copied into each walk workgroup's LDS, and a neighbour whose bit is clear
+// skips its rank-directory gather (it cannot be a survivor).  A set bit
+// proves nothing; the directory still decides.
+constexpr int kFiltShift = 16;
+constexpr int kFiltBits = 1 << kFiltShift;       // 65536 bits: 8 KB
+constexpr int kFiltWords = kFiltBits / 32;
+
+__device__ __host__ inline uint32_t filt_hash(uint32_t v) {
+    return (v * 0x9E3779B1u) >> (32 - kFiltShift);  // Fibonacci hashing
+}
 
 // Device status codes (kept in DevState::status; mapped to dsg_status).
 enum : int32_t {
@@ -80,6 +94,7 @@ struct alignas(256) DevState {
     int32_t force_bins;   // 1: always use bin regions (launch flag)
     int32_t apply_lanes;  // lanes that share one tile's run in k_apply (4..64)
     int32_t reduce_lanes; // lanes that share one rank in k_reduce (1..16)
+    int32_t use_filt;     // 1: this pass's survivors are in the walk's survivor filter
     // k-core levels (CBDS-P phase 1): the threshold is the level k and stays
     // there while passes remove vertices; a pass that removes none ends the
     // level, and the next level is the least degree left

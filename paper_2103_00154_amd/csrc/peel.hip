@@ -83,6 +83,7 @@ struct Work {
     int32_t* partial;     // items x part_stride: per-item counts
     uint16_t* recs;       // walk tiles x kWalkTile: 16-bit local ranks
     uint16_t* toff;       // walk tiles x (bins + 1): bin offsets inside each tile
+    uint32_t* filt;       // kFiltWords: survivor filter of the current pass
     PassRecord* trace;    // kTraceCap
 };
 
@@ -162,6 +163,7 @@ __global__ void k_init_state(Work w, const int32_t* __restrict__ rp, int64_t n, 
     st->force_bins = force_bins;
     st->apply_lanes = 64;
     st->reduce_lanes = 16;
+    st->use_filt = 0;
     if (rp[0] != 0 || (int64_t)rp[n] != 2 * m) {
         st->status = kStBadRowPtr;
         st->done = 1;
@@ -356,6 +358,10 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode,
     int64_t pe = block_excl_sum<int64_t, kScanBlock / 64>(e, red, &te);
     int64_t pds = block_excl_sum<int64_t, kScanBlock / 64>(ds, red, &tds);
     const int64_t tdr = block_sum<int64_t, kScanBlock / 64>(dr, red);
+    // few survivors: k_mark_scatter sets their bits in a cleared filter
+    const bool filt = mode == 0 && tl > 0 && tl <= kFiltBits;
+    if (filt)
+        for (int i = threadIdx.x; i < kFiltWords; i += kScanBlock) w.filt[i] = 0u;
 #pragma unroll 8
     for (int64_t i = lo; i < hi; ++i) {
         const int4 c = w.tiles[2 * i];
@@ -379,6 +385,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode,
             st->nbins = (int32_t)((tl + kBinWidth - 1) >> kBinShift);
             st->walk_mode = (st->nbins <= kNbLds && !st->force_bins) ? 0 : 1;
             st->toff_stride = st->nbins + 1;
+            st->use_filt = filt ? 1 : 0;
             st->tot_live += items;
             st->tot_alist += ta;
             st->cross = 0;
@@ -405,6 +412,7 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
     const int32_t* __restrict__ din = deg_in(w, pass);
     int32_t* __restrict__ lout = live_out(w, pass);
     int32_t* __restrict__ dout = deg_out(w, pass);
+    const bool filt = st->use_filt != 0;
     const int64_t ntiles = (S + kMarkTile - 1) / kMarkTile;
     __shared__ uint32_t red[kWaves];
 
@@ -497,6 +505,10 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
             } else if (pL < n) {
                 lout[pL] = v;
                 dout[pL] = dd[j];
+                if (filt) {
+                    const uint32_t h = filt_hash((uint32_t)v);
+                    atomicOr(&w.filt[h >> 5], 1u << (h & 31));
+                }
                 if ((pL & (kBinWidth - 1)) == 0 && (pL >> kBinShift) < bin_cap) {
                     w.bin_start[pL >> kBinShift] = (int32_t)pD;
                     w.bin_cur[pL >> kBinShift] = (int32_t)pD;
@@ -689,15 +701,24 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
     const int32_t* __restrict__ aoff = w.aoff;
     const int32_t* __restrict__ arow = w.arow;
     const int tid = threadIdx.x;
+    const bool filt = st->use_filt != 0;
 
-    __shared__ __align__(16) int32_t own[kWalkTile];
+    __shared__ __align__(16) uint16_t own[kWalkTile];
     __shared__ int32_t bas[kWalkTile + 1];
+    __shared__ __align__(16) uint32_t filt_s[kFiltWords];
     __shared__ int32_t tcount[kNbLds];  // per-tile bin counts, then their offsets
     __shared__ int32_t wtot[kWaves][kWaveAggBins];  // per-wave bin counts (few bins)
     __shared__ int32_t red[kWaves];
     __shared__ unsigned long long redc[kWaves];
     __shared__ int32_t s_last;
     __shared__ int32_t s_keep;
+
+    if (filt && (int32_t)blockIdx.x < ntiles) {
+        // read before the first tile's barriers
+        const uint4* __restrict__ src = reinterpret_cast<const uint4*>(w.filt);
+        uint4* dst = reinterpret_cast<uint4*>(filt_s);
+        for (int i = tid; i < kFiltWords / 4; i += kBlock) dst[i] = src[i];
+    }
 
     uint32_t cross = 0;
     for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -714,58 +735,105 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
 
         // 1. owner of every entry of the tile: rows start at strictly
         //    increasing offsets, so a running max over the start marks works
-        constexpr int kQ = kWalkItems / 4;  // int4 words of own[] per thread
-        int4* own4 = reinterpret_cast<int4*>(own);
+        //    (indices < kWalkTile + 1 fit 16 bits; 8 per 16-byte word)
+        constexpr int kQ = kWalkItems / 8;  // 16-byte words of own[] per thread
+        uint4* own4 = reinterpret_cast<uint4*>(own);
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) own4[kQ * tid + q] = make_int4(0, 0, 0, 0);
+        for (int q = 0; q < kQ; ++q) own4[kQ * tid + q] = make_uint4(0u, 0u, 0u, 0u);
         if (lds_bins)
             for (int b = tid; b < nb; b += kBlock) tcount[b] = 0;
         __syncthreads();
-        for (int32_t i = tid; i < c; i += kBlock) {
-            const int32_t off = aoff[i0 + i];
-            bas[i] = arow[i0 + i] - off;
-            const int32_t o = off - (int32_t)e0;
-            if (o < len) own[o > 0 ? o : 0] = i;
+        // rows in rounds of four per thread, every load of a round issued
+        // before any is used (indices clamped to the last row)
+        for (int32_t r0 = 0; r0 < c; r0 += 4 * kBlock) {
+            int32_t ao[4], ar[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int32_t i = min(r0 + q * kBlock + tid, c - 1);
+                ao[q] = aoff[i0 + i];
+                ar[q] = arow[i0 + i];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int32_t i = r0 + q * kBlock + tid;
+                if (i < c) {
+                    bas[i] = ar[q] - ao[q];
+                    const int32_t o = ao[q] - (int32_t)e0;
+                    if (o < len) own[o > 0 ? o : 0] = (uint16_t)i;
+                }
+            }
         }
         __syncthreads();
         {
-            int4 q4[kQ];
+            uint4 q4[kQ];
 #pragma unroll
             for (int q = 0; q < kQ; ++q) q4[q] = own4[kQ * tid + q];
-            int32_t run = 0;
+            uint32_t run = 0;
+            auto step = [&run](uint32_t x) {
+                const uint32_t lo = run = max(run, x & 0xFFFFu);
+                const uint32_t hi = run = max(run, x >> 16);
+                return lo | (hi << 16);
+            };
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
-                q4[q].x = run = max(run, q4[q].x);
-                q4[q].y = run = max(run, q4[q].y);
-                q4[q].z = run = max(run, q4[q].z);
-                q4[q].w = run = max(run, q4[q].w);
+                q4[q].x = step(q4[q].x);
+                q4[q].y = step(q4[q].y);
+                q4[q].z = step(q4[q].z);
+                q4[q].w = step(q4[q].w);
             }
-            const int32_t carry = block_excl_max(run, red, 0);
+            const uint32_t carry = (uint32_t)block_excl_max((int32_t)run, red, 0);
+            auto lift = [carry](uint32_t x) {
+                return max(x & 0xFFFFu, carry) | (max(x >> 16, carry) << 16);
+            };
 #pragma unroll
             for (int q = 0; q < kQ; ++q)
-                own4[kQ * tid + q] = make_int4(max(q4[q].x, carry), max(q4[q].y, carry),
-                                               max(q4[q].z, carry), max(q4[q].w, carry));
+                own4[kQ * tid + q] = make_uint4(lift(q4[q].x), lift(q4[q].y), lift(q4[q].z),
+                                                lift(q4[q].w));
         }
         __syncthreads();
 
-        // 2. neighbour ids (coalesced: consecutive lanes, consecutive entries)
+        // 2. neighbour ids (coalesced: consecutive lanes, consecutive
+        //    entries).  All owner reads, then all row-base reads, then all
+        //    loads, with clamped indices and no load inside a branch (lanes
+        //    past the tile end re-read its last entry), so each group is in
+        //    flight at once; validity is applied after the last load.
         int32_t u[kWalkItems];
+        {
+            int32_t rb[kWalkItems];
 #pragma unroll
-        for (int j = 0; j < kWalkItems; ++j) {
-            const int p = j * kBlock + tid;
-            const uint32_t pos = (uint32_t)bas[own[p]] + (e0 + (uint32_t)p);
-            int32_t x = -1;
-            if (p < len && pos < nnz) x = __builtin_nontemporal_load(ci + pos);
-            u[j] = (uint32_t)x < n ? x : -1;  // ids outside 0..n-1 are ignored
+            for (int j = 0; j < kWalkItems; ++j) rb[j] = own[min(j * kBlock + tid, len - 1)];
+#pragma unroll
+            for (int j = 0; j < kWalkItems; ++j) rb[j] = bas[rb[j]];
+#pragma unroll
+            for (int j = 0; j < kWalkItems; ++j) {
+                const uint32_t p = (uint32_t)min(j * kBlock + tid, len - 1);
+                const uint32_t pos = min((uint32_t)rb[j] + e0 + p, nnz - 1u);
+                u[j] = __builtin_nontemporal_load(ci + pos);
+            }
+#pragma unroll
+            for (int j = 0; j < kWalkItems; ++j)  // ids outside 0..n-1 are ignored
+                if (j * kBlock + tid >= len || (uint32_t)u[j] >= n) u[j] = -1;
         }
-        // 3. survivor rank of every neighbour still present, else -1
+        // 3. survivor rank of every neighbour still present, else -1.  A
+        //    neighbour outside the survivor filter gathers word 0 instead (one
+        //    line for the whole wave) and is known not to survive.
+        bool cand[kWalkItems];
+#pragma unroll
+        for (int j = 0; j < kWalkItems; ++j) cand[j] = u[j] >= 0;
+        if (filt) {
+#pragma unroll
+            for (int j = 0; j < kWalkItems; ++j) {
+                const uint32_t h = filt_hash((uint32_t)u[j]);
+                cand[j] = cand[j] && ((filt_s[h >> 5] >> (h & 31)) & 1u);
+            }
+        }
         int32_t rk[kWalkItems];
 #pragma unroll
         for (int j = 0; j < kWalkItems; ++j) {
-            const uint32_t x = (uint32_t)max(u[j], 0);
+            const uint32_t x = cand[j] ? (uint32_t)u[j] : 0u;
             const uint2 d = dir[x >> 5];
             const uint32_t bit = 1u << (x & 31);
-            rk[j] = (u[j] >= 0 && (d.x & bit)) ? (int32_t)(d.y + __popc(d.x & (bit - 1u))) : -1;
+            rk[j] = (cand[j] && (d.x & bit)) ? (int32_t)(d.y + __popc(d.x & (bit - 1u))) : -1;
         }
         if (lds_bins) {
             // 4. slot of every record inside its (tile, bin) group
@@ -1200,7 +1268,7 @@ inline int64_t max_items(int64_t n, int64_t m) {
 
 struct Layout {
     size_t st, rem, dir, l0, l1, d0, d1, arow, aoff, tfirst, tiles, bstart, bcur, bitems, items,
-        partial, recs, toff, trace, total;
+        partial, recs, toff, filt, trace, total;
 };
 
 Layout layout(int64_t n, int64_t m) {
@@ -1231,6 +1299,7 @@ Layout layout(int64_t n, int64_t m) {
     L.partial = take(4 * (size_t)ni * (size_t)part_stride(n));
     L.recs = take(2 * (size_t)walk_tiles(m) * kWalkTile);
     L.toff = take(2 * (size_t)walk_tiles(m) * (size_t)(std::min<int64_t>(nb, kNbLds) + 1));
+    L.filt = take(4 * (size_t)kFiltWords);
     L.trace = take(sizeof(PassRecord) * (size_t)kTraceCap);
     L.total = o;
     return L;
@@ -1374,6 +1443,7 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
     w.partial = (int32_t*)(base + L.partial);
     w.recs = (uint16_t*)(base + L.recs);
     w.toff = (uint16_t*)(base + L.toff);
+    w.filt = (uint32_t*)(base + L.filt);
     w.trace = (PassRecord*)(base + L.trace);
 
     // core levels: every pass removes a vertex or ends a level, and every
