@@ -25,7 +25,6 @@ constexpr int32_t kNever = INT32_MAX;            // removed_at of a vertex still
 constexpr int kBinShift = 15;
 constexpr int kBinWidth = 1 << kBinShift;        // 32768 ranks: 128 KB of LDS counters
 constexpr int kNbLds = 1024;                     // bins the walk can stage in LDS
-constexpr int kWaveAggBins = 8;                  // up to this many bins, slots per wave
 constexpr int kScanBlock = 256;                  // threads of the tile-scan workgroup
 constexpr int kApplyBlock = 1024;                // threads of an apply workgroup
 constexpr int kApplyBatch = 8;                   // record loads per lane before counting

@@ -694,7 +694,7 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
     const int32_t ntiles = st->nL > 0 ? st->n_tiles_walk : 0;
     const int32_t nb = st->nbins;
     const bool lds_bins = st->walk_mode == 0;
-    const bool wave_slots = nb <= kWaveAggBins;
+    const bool one_bin = nb == 1;
     const uint2* __restrict__ dir = w.dir;
     int32_t* __restrict__ bin_cur = w.bin_cur;
     uint16_t* __restrict__ recs = w.recs;
@@ -707,7 +707,7 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
     __shared__ int32_t bas[kWalkTile + 1];
     __shared__ __align__(16) uint32_t filt_s[kFiltWords];
     __shared__ int32_t tcount[kNbLds];  // per-tile bin counts, then their offsets
-    __shared__ int32_t wtot[kWaves][kWaveAggBins];  // per-wave bin counts (few bins)
+    __shared__ int32_t wtot[kWaves];  // per-wave record counts (one bin)
     __shared__ int32_t red[kWaves];
     __shared__ unsigned long long redc[kWaves];
     __shared__ int32_t s_last;
@@ -838,47 +838,32 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
         if (lds_bins) {
             // 4. slot of every record inside its (tile, bin) group
             int32_t slot[kWalkItems];
-            if (wave_slots) {
-                // few bins: ballots give each lane its rank among the wave's
-                // records of its bin (items in order, lanes in order); a
-                // table of per-wave totals then orders the waves
-                int32_t run[kWaveAggBins];
-#pragma unroll
-                for (int b = 0; b < kWaveAggBins; ++b) run[b] = 0;
+            if (one_bin) {
+                // one bin (at most kBinWidth survivors): a lane's slot is the
+                // number of the wave's records before it (items in order,
+                // lanes in order) plus the records of the waves before
+                int32_t run = 0;
 #pragma unroll
                 for (int j = 0; j < kWalkItems; ++j) {
-                    const int32_t my_bin = rk[j] >= 0 ? rk[j] >> kBinShift : -1;
-                    slot[j] = 0;
-#pragma unroll
-                    for (int b = 0; b < kWaveAggBins; ++b) {
-                        if (b < nb) {
-                            const unsigned long long m = __ballot(my_bin == b);
-                            if (my_bin == b) slot[j] = run[b] + lanes_below(m);
-                            run[b] += (int32_t)__popcll(m);
-                        }
-                    }
+                    const unsigned long long m = __ballot(rk[j] >= 0);
+                    slot[j] = run + lanes_below(m);
+                    run += (int32_t)__popcll(m);
                 }
-                if (lane_id() == 0)
-                    for (int b = 0; b < nb; ++b) wtot[wave_id()][b] = run[b];
+                if (lane_id() == 0) wtot[wave_id()] = run;
                 __syncthreads();
-                if (tid < nb) {
-                    int32_t s = 0;
+                int32_t before = 0, all = 0;
 #pragma unroll
-                    for (int v = 0; v < kWaves; ++v) s += wtot[v][tid];
-                    tcount[tid] = s;
+                for (int v = 0; v < kWaves; ++v) {
+                    before += v < wave_id() ? wtot[v] : 0;
+                    all += wtot[v];
                 }
+                if (tid == 0) tcount[0] = all;
 #pragma unroll
-                for (int j = 0; j < kWalkItems; ++j) {
-                    if (rk[j] >= 0) {
-                        const int32_t b = rk[j] >> kBinShift;
-                        int32_t before = 0;
-                        for (int v = 0; v < wave_id(); ++v) before += wtot[v][b];
-                        slot[j] += before;
-                    }
-                }
+                for (int j = 0; j < kWalkItems; ++j) slot[j] += before;
             } else {
-                // many bins: one LDS atomic per record; the returns are
-                // independent, so they pipeline
+                // several bins: one LDS atomic per record; the returns are
+                // independent, so they pipeline (measured faster than one
+                // ballot per bin and item from two bins up)
 #pragma unroll
                 for (int j = 0; j < kWalkItems; ++j)
                     slot[j] = rk[j] >= 0 ? atomicAdd(&tcount[rk[j] >> kBinShift], 1) : 0;
