@@ -88,7 +88,7 @@ typedef struct {
  * depend on these. */
 typedef struct {
     int32_t mark_grid;  /* workgroups of the mark / extract kernels */
-    int32_t walk_grid;  /* workgroups of the neighbour-walk kernel  */
+    int32_t walk_grid;  /* workgroups of the neighbour-walk kernel (at most 4096 are used) */
     int32_t pass_batch; /* passes enqueued before the host checks for completion */
     int32_t flags;      /* DSG_LAUNCH_* bits */
 } dsg_launch;

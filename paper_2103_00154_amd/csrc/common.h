@@ -13,6 +13,8 @@ constexpr int kMarkItems = 8;                    // live-list entries per thread
 constexpr int kMarkTile = kBlock * kMarkItems;   // live-list entries per tile
 constexpr int kWalkItems = 16;                   // adjacency entries per thread
 constexpr int kWalkTile = kBlock * kWalkItems;   // adjacency entries per tile
+constexpr int kFewRows = 4;                      // tiles over <= this many rows skip the owner table
+constexpr int kMaxWalkGrid = 4096;               // walk workgroups (one partial count each)
 static_assert(kWalkItems % 8 == 0, "the owner scan moves 16-byte words of 16-bit entries");
 static_assert(kWalkTile < 65536, "owner indices are 16-bit");
 constexpr int kTraceCap = 4096;                  // device trace records
@@ -68,7 +70,7 @@ struct alignas(256) DevState {
     int64_t edges;      // adjacency entries of the walk list
     int64_t sumdeg;     // sum of the current degrees of all failed vertices
     int64_t sumdeg_surv;  // sum of the current degrees of the survivors
-    unsigned long long cross;  // survivors' degree decrements, summed by walk blocks
+    unsigned long long cross;  // survivors' degree decrements (sum of the walk partials)
     int64_t best_count; // ids written by the extract kernels
     int64_t tot_walked; // statistics over all passes
     int64_t tot_cross;
@@ -80,7 +82,6 @@ struct alignas(256) DevState {
     int32_t best_pass;
     int32_t done;       // 1 once the graph is empty or an error is recorded
     int32_t status;
-    uint32_t ticket;    // last-block-done counter of the walk kernel
     int32_t max_pass;   // watchdog bound
     int32_t trace_cap;  // records the device trace may hold
     int32_t n_tiles_walk;  // walk tiles of the current pass

@@ -1,7 +1,7 @@
 // peel.hip - Bahmani's (2+2eps) peeling passes on gfx950 and the C ABI of
 // libdsg.so (include/dsg.h).
 //
-// One pass of Algorithm 1 (P-Bahmani, Section 3.1) runs as six kernels on
+// One pass of Algorithm 1 (P-Bahmani, Section 3.1) runs as seven kernels on
 // the caller's stream:
 //
 //   k_mark_count    part 1, the failure test, over the live list L_{k-1}
@@ -22,10 +22,12 @@
 //                   hub rows spread over many workgroups.  A neighbour still
 //                   present gets its survivor rank from the rank directory,
 //                   and a 16-bit record of it is appended to its rank bin;
-//                   a tile reserves space once per bin it touches.  The last
-//                   workgroup reduces |V| and |E|, keeps the best graph,
-//                   derives the next threshold and splits the bins into
-//                   apply work items.
+//                   a tile reserves space once per bin it touches.  A
+//                   neighbour outside the pass's survivor filter (few
+//                   survivors) skips the rank-directory lookup.
+//   k_walk_finish   one workgroup: sums the walk workgroups' record counts,
+//                   reduces |V| and |E|, keeps the best graph, derives the
+//                   next threshold and splits the bins into apply work items.
 //   k_apply         the degree decrements.  Each work item counts its records
 //                   in LDS (one counter per rank of the bin) and writes the
 //                   counts as one partial row.
@@ -84,6 +86,7 @@ struct Work {
     uint16_t* recs;       // walk tiles x kWalkTile: 16-bit local ranks
     uint16_t* toff;       // walk tiles x (bins + 1): bin offsets inside each tile
     uint32_t* filt;       // kFiltWords: survivor filter of the current pass
+    unsigned long long* wpart;  // kMaxWalkGrid: decrement records per walk workgroup
     PassRecord* trace;    // kTraceCap
 };
 
@@ -150,7 +153,6 @@ __global__ void k_init_state(Work w, const int32_t* __restrict__ rp, int64_t n, 
     st->cb_sumlegit = st->cb_el = 0;
     st->done = 0;
     st->status = kStOk;
-    st->ticket = 0;
     st->max_pass = max_pass;
     st->trace_cap = trace_cap;
     st->n_tiles_walk = 0;
@@ -389,7 +391,6 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode,
             st->tot_live += items;
             st->tot_alist += ta;
             st->cross = 0;
-            st->ticket = 0;
             w.aoff[ta] = (int32_t)te;
             w.bin_start[st->nbins] = (int32_t)tds;
         } else {
@@ -521,13 +522,13 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
 }
 
 // --------------------------------------------------------- pass completion
-// Run by every thread of the last walk workgroup.
+// Run by every thread of k_walk_finish's workgroup.
 
 __device__ void finish_pass(const Work& w, int32_t* s_flag, int32_t* red) {
     DevState* st = w.st;
     if (threadIdx.x == 0) {
         int32_t keep = 1;
-        const int64_t cross = (int64_t)atomic_load_u64(&st->cross);
+        const int64_t cross = (int64_t)st->cross;
         const int64_t S_in = st->S, E_in = st->E;
         const int64_t S_out = st->nL;
         const int64_t intra = st->sumdeg - cross;
@@ -567,7 +568,6 @@ __device__ void finish_pass(const Work& w, int32_t* s_flag, int32_t* red) {
             }
             st->S = S_out;
             st->E = E_out;
-            __hip_atomic_store(&st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (S_out == 0) {
                 st->done = 1;
                 keep = 0;
@@ -710,8 +710,6 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
     __shared__ int32_t wtot[kWaves];  // per-wave record counts (one bin)
     __shared__ int32_t red[kWaves];
     __shared__ unsigned long long redc[kWaves];
-    __shared__ int32_t s_last;
-    __shared__ int32_t s_keep;
 
     if (filt && (int32_t)blockIdx.x < ntiles) {
         // read before the first tile's barriers
@@ -733,87 +731,112 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
         }
         const int32_t c = ihi - i0 + 1;
 
-        // 1. owner of every entry of the tile: rows start at strictly
-        //    increasing offsets, so a running max over the start marks works
-        //    (indices < kWalkTile + 1 fit 16 bits; 8 per 16-byte word)
-        constexpr int kQ = kWalkItems / 8;  // 16-byte words of own[] per thread
-        uint4* own4 = reinterpret_cast<uint4*>(own);
+        // 1. row base (CSR row start minus walk offset) of every entry.  A
+        //    tile inside at most kFewRows rows compares each position with
+        //    the row starts (the same values in every lane); a longer span
+        //    builds an owner table in LDS: rows start at strictly increasing
+        //    offsets, so a running max over the start marks works (indices
+        //    < kWalkTile + 1 fit 16 bits; 8 per 16-byte word).
+        int32_t rb[kWalkItems];
+        if (c <= kFewRows) {
+            int32_t fo[kFewRows], fb[kFewRows];
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) own4[kQ * tid + q] = make_uint4(0u, 0u, 0u, 0u);
-        if (lds_bins)
-            for (int b = tid; b < nb; b += kBlock) tcount[b] = 0;
-        __syncthreads();
-        // rows in rounds of four per thread, every load of a round issued
-        // before any is used (indices clamped to the last row)
-        for (int32_t r0 = 0; r0 < c; r0 += 4 * kBlock) {
-            int32_t ao[4], ar[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int32_t i = min(r0 + q * kBlock + tid, c - 1);
-                ao[q] = aoff[i0 + i];
-                ar[q] = arow[i0 + i];
+            for (int r = 0; r < kFewRows; ++r) {
+                // rows past the span repeat the last one, which selects the same
+                const int32_t i = i0 + min(r, c - 1);
+                const int32_t ao = aoff[i];
+                fo[r] = ao - (int32_t)e0;
+                fb[r] = arow[i] - ao;
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int32_t i = r0 + q * kBlock + tid;
-                if (i < c) {
-                    bas[i] = ar[q] - ao[q];
-                    const int32_t o = ao[q] - (int32_t)e0;
-                    if (o < len) own[o > 0 ? o : 0] = (uint16_t)i;
+            for (int j = 0; j < kWalkItems; ++j) {
+                const int32_t p = min(j * kBlock + tid, len - 1);
+                int32_t b = fb[0];
+#pragma unroll
+                for (int r = 1; r < kFewRows; ++r) b = fo[r] <= p ? fb[r] : b;
+                rb[j] = b;
+            }
+            if (lds_bins && !one_bin) {
+                for (int b = tid; b < nb; b += kBlock) tcount[b] = 0;
+                __syncthreads();
+            }
+        } else {
+            constexpr int kQ = kWalkItems / 8;  // 16-byte words of own[] per thread
+            uint4* own4 = reinterpret_cast<uint4*>(own);
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) own4[kQ * tid + q] = make_uint4(0u, 0u, 0u, 0u);
+            if (lds_bins)
+                for (int b = tid; b < nb; b += kBlock) tcount[b] = 0;
+            __syncthreads();
+            // rows in rounds of four per thread, every load of a round issued
+            // before any is used (indices clamped to the last row)
+            for (int32_t r0 = 0; r0 < c; r0 += 4 * kBlock) {
+                int32_t ao[4], ar[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t i = min(r0 + q * kBlock + tid, c - 1);
+                    ao[q] = aoff[i0 + i];
+                    ar[q] = arow[i0 + i];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t i = r0 + q * kBlock + tid;
+                    if (i < c) {
+                        bas[i] = ar[q] - ao[q];
+                        const int32_t o = ao[q] - (int32_t)e0;
+                        if (o < len) own[o > 0 ? o : 0] = (uint16_t)i;
+                    }
                 }
             }
-        }
-        __syncthreads();
-        {
-            uint4 q4[kQ];
+            __syncthreads();
+            {
+                uint4 q4[kQ];
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) q4[q] = own4[kQ * tid + q];
-            uint32_t run = 0;
-            auto step = [&run](uint32_t x) {
-                const uint32_t lo = run = max(run, x & 0xFFFFu);
-                const uint32_t hi = run = max(run, x >> 16);
-                return lo | (hi << 16);
-            };
+                for (int q = 0; q < kQ; ++q) q4[q] = own4[kQ * tid + q];
+                uint32_t run = 0;
+                auto step = [&run](uint32_t x) {
+                    const uint32_t lo = run = max(run, x & 0xFFFFu);
+                    const uint32_t hi = run = max(run, x >> 16);
+                    return lo | (hi << 16);
+                };
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) {
-                q4[q].x = step(q4[q].x);
-                q4[q].y = step(q4[q].y);
-                q4[q].z = step(q4[q].z);
-                q4[q].w = step(q4[q].w);
+                for (int q = 0; q < kQ; ++q) {
+                    q4[q].x = step(q4[q].x);
+                    q4[q].y = step(q4[q].y);
+                    q4[q].z = step(q4[q].z);
+                    q4[q].w = step(q4[q].w);
+                }
+                const uint32_t carry = (uint32_t)block_excl_max((int32_t)run, red, 0);
+                auto lift = [carry](uint32_t x) {
+                    return max(x & 0xFFFFu, carry) | (max(x >> 16, carry) << 16);
+                };
+#pragma unroll
+                for (int q = 0; q < kQ; ++q)
+                    own4[kQ * tid + q] = make_uint4(lift(q4[q].x), lift(q4[q].y), lift(q4[q].z),
+                                                    lift(q4[q].w));
             }
-            const uint32_t carry = (uint32_t)block_excl_max((int32_t)run, red, 0);
-            auto lift = [carry](uint32_t x) {
-                return max(x & 0xFFFFu, carry) | (max(x >> 16, carry) << 16);
-            };
-#pragma unroll
-            for (int q = 0; q < kQ; ++q)
-                own4[kQ * tid + q] = make_uint4(lift(q4[q].x), lift(q4[q].y), lift(q4[q].z),
-                                                lift(q4[q].w));
-        }
-        __syncthreads();
+            __syncthreads();
 
-        // 2. neighbour ids (coalesced: consecutive lanes, consecutive
-        //    entries).  All owner reads, then all row-base reads, then all
-        //    loads, with clamped indices and no load inside a branch (lanes
-        //    past the tile end re-read its last entry), so each group is in
-        //    flight at once; validity is applied after the last load.
-        int32_t u[kWalkItems];
-        {
-            int32_t rb[kWalkItems];
 #pragma unroll
             for (int j = 0; j < kWalkItems; ++j) rb[j] = own[min(j * kBlock + tid, len - 1)];
 #pragma unroll
             for (int j = 0; j < kWalkItems; ++j) rb[j] = bas[rb[j]];
-#pragma unroll
-            for (int j = 0; j < kWalkItems; ++j) {
-                const uint32_t p = (uint32_t)min(j * kBlock + tid, len - 1);
-                const uint32_t pos = min((uint32_t)rb[j] + e0 + p, nnz - 1u);
-                u[j] = __builtin_nontemporal_load(ci + pos);
-            }
-#pragma unroll
-            for (int j = 0; j < kWalkItems; ++j)  // ids outside 0..n-1 are ignored
-                if (j * kBlock + tid >= len || (uint32_t)u[j] >= n) u[j] = -1;
         }
+
+        // 2. neighbour ids (coalesced: consecutive lanes, consecutive
+        //    entries), all loads issued before any is used, with clamped
+        //    indices and no load inside a branch (lanes past the tile end
+        //    re-read its last entry); validity is applied after the last load.
+        int32_t u[kWalkItems];
+#pragma unroll
+        for (int j = 0; j < kWalkItems; ++j) {
+            const uint32_t p = (uint32_t)min(j * kBlock + tid, len - 1);
+            const uint32_t pos = min((uint32_t)rb[j] + e0 + p, nnz - 1u);
+            u[j] = __builtin_nontemporal_load(ci + pos);
+        }
+#pragma unroll
+        for (int j = 0; j < kWalkItems; ++j)  // ids outside 0..n-1 are ignored
+            if (j * kBlock + tid >= len || (uint32_t)u[j] >= n) u[j] = -1;
         // 3. survivor rank of every neighbour still present, else -1.  A
         //    neighbour outside the survivor filter gathers word 0 instead (one
         //    line for the whole wave) and is known not to survive.
@@ -909,16 +932,26 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
         }
         __syncthreads();
     }
+    // one slot per workgroup, summed by k_walk_finish (same-address device
+    // atomics from every workgroup serialise at about 15 ns each)
     const unsigned long long bc = block_sum((unsigned long long)cross, redc);
-    if (tid == 0) {
-        if (bc) atomicAdd(&st->cross, bc);
-        __threadfence();
-        const uint32_t tk = atomicAdd(&st->ticket, 1u);
-        s_last = tk == gridDim.x - 1;
-        if (s_last) __threadfence();
-    }
+    if (tid == 0) w.wpart[blockIdx.x] = bc;
+}
+
+// Sums the walk workgroups' record counts and completes the pass: |V|, |E|,
+// the best graph, the next threshold and the apply work items.
+__global__ __launch_bounds__(kBlock) void k_walk_finish(Work w, int32_t parts) {
+    DevState* st = w.st;
+    if (st->done) return;
+    __shared__ int32_t red[kWaves];
+    __shared__ unsigned long long redc[kWaves];
+    __shared__ int32_t s_keep;
+    unsigned long long c = 0;
+    for (int32_t i = threadIdx.x; i < parts; i += kBlock) c += w.wpart[i];
+    c = block_sum(c, redc);
+    if (threadIdx.x == 0) st->cross = c;
     __syncthreads();
-    if (s_last) finish_pass(w, &s_keep, red);
+    finish_pass(w, &s_keep, red);
 }
 
 // ----------------------------------------------------------------- apply
@@ -1253,7 +1286,7 @@ inline int64_t max_items(int64_t n, int64_t m) {
 
 struct Layout {
     size_t st, rem, dir, l0, l1, d0, d1, arow, aoff, tfirst, tiles, bstart, bcur, bitems, items,
-        partial, recs, toff, filt, trace, total;
+        partial, recs, toff, filt, wpart, trace, total;
 };
 
 Layout layout(int64_t n, int64_t m) {
@@ -1285,6 +1318,7 @@ Layout layout(int64_t n, int64_t m) {
     L.recs = take(2 * (size_t)walk_tiles(m) * kWalkTile);
     L.toff = take(2 * (size_t)walk_tiles(m) * (size_t)(std::min<int64_t>(nb, kNbLds) + 1));
     L.filt = take(4 * (size_t)kFiltWords);
+    L.wpart = take(8 * (size_t)kMaxWalkGrid);
     L.trace = take(sizeof(PassRecord) * (size_t)kTraceCap);
     L.total = o;
     return L;
@@ -1429,6 +1463,7 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
     w.recs = (uint16_t*)(base + L.recs);
     w.toff = (uint16_t*)(base + L.toff);
     w.filt = (uint32_t*)(base + L.filt);
+    w.wpart = (unsigned long long*)(base + L.wpart);
     w.trace = (PassRecord*)(base + L.trace);
 
     // core levels: every pass removes a vertex or ends a level, and every
@@ -1442,7 +1477,7 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
         int64_t wg = launch && launch->walk_grid ? launch->walk_grid
                                                  : (int64_t)di.cus * di.walk_blocks_per_cu;
         mark_grid = (unsigned)std::max<int64_t>(1, std::min(mg, mt));
-        walk_grid = (unsigned)std::max<int64_t>(1, std::min(wg, wt));
+        walk_grid = (unsigned)std::max<int64_t>(1, std::min({wg, wt, (int64_t)kMaxWalkGrid}));
         init_grid = (unsigned)std::max<int64_t>(
             1, std::min<int64_t>((int64_t)di.cus * 8, (n + kBlock - 1) / kBlock));
         apply_grid = (unsigned)std::max<int64_t>(
@@ -1476,6 +1511,7 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
             DSG_HIP(hipGetLastError());
             DSG_HIP(log.end());
             DSG_HIP(log.begin(kKindApply));
+            k_walk_finish<<<1, kBlock, 0, s>>>(w, (int32_t)walk_grid);
             k_apply<<<apply_grid, kApplyBlock, 0, s>>>(w);
             k_reduce<<<reduce_grid, kBlock, 0, s>>>(w);
             DSG_HIP(hipGetLastError());
@@ -1507,8 +1543,9 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
             const int64_t cap = (int64_t)di.cus * 8;
             mark_grid = (unsigned)std::max<int64_t>(1, std::min(cap, mark_tiles(S) - 1));
             walk_grid = (unsigned)std::max<int64_t>(
-                1, std::min<int64_t>((int64_t)di.cus * di.walk_blocks_per_cu,
-                                     std::max<int64_t>(mark_grid, di.cus)));
+                1, std::min<int64_t>({(int64_t)di.cus * di.walk_blocks_per_cu,
+                                      std::max<int64_t>(mark_grid, di.cus),
+                                      (int64_t)kMaxWalkGrid}));
             reduce_grid = (unsigned)std::max<int64_t>(1, std::min(cap, (S * 16 + kBlock - 1) / kBlock));
         }
     }
