@@ -414,6 +414,8 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
     int32_t* __restrict__ lout = live_out(w, pass);
     int32_t* __restrict__ dout = deg_out(w, pass);
     const bool filt = st->use_filt != 0;
+    // a pass that leaves no survivor walks nothing: no walk tiles to mark
+    const int64_t wcap = st->nL > 0 ? walk_cap : 0;
     const int64_t ntiles = (S + kMarkTile - 1) / kMarkTile;
     __shared__ uint32_t red[kWaves];
 
@@ -498,7 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
                     const int64_t len = ll[j];
                     // walk tiles whose first entry lies in [pE, pE + len)
                     for (int64_t tt = (pE + kWalkTile - 1) / kWalkTile;
-                         tt * kWalkTile < pE + len && tt < walk_cap; ++tt)
+                         tt * kWalkTile < pE + len && tt < wcap; ++tt)
                         w.tile_first[tt] = (int32_t)pA;
                     ++pA;
                     pE += len;
