@@ -55,6 +55,7 @@ constexpr uint32_t kStSlot0 = 0xFE00u;   // present, degree in big-degree slot s
 constexpr int kSlots = (int)(kStGlobal - kStSlot0);
 constexpr int kBMarkItems = 4;           // live-list entries per thread per mark chunk
 constexpr int kMinWaveTile = 64 * 4;     // smallest wave tile (sizes the tile table)
+constexpr int32_t kNoStart = INT32_MIN;  // no row starts at this entry (row bases are larger)
 constexpr uint64_t kPlanMagic = 0x44534742504c414eull;
 
 // One graph of the batch, in queue order (device copy).
@@ -307,66 +308,95 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
             uint32_t cross = 0, intra = 0, badc = 0;
             if (nL > 0 && W > 0) {
                 const int32_t ntile = (W + WT - 1) / WT;
-                for (int k = lane; k < WT; k += 64) own[k] = 0;
-                // software pipeline: the row holding a tile's first entry and
-                // the starts of the 256 rows after it are loaded one tile
-                // ahead, while the wave works on the previous tile
+                // software pipeline: the row holding a tile's first entry, its
+                // base, and the starts and bases of the 256 rows after it are
+                // loaded one tile ahead, while the wave works on the previous
+                // tile
                 int32_t rc = wid < ntile ? tf[wid] : 0;
-                int32_t pst[4];
+                int32_t bc = abase[rc];
+                int32_t pst[4], pab[4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) pst[k] = apre[min(rc + 1 + 64 * k + lane, nA - 1)];
+                for (int k = 0; k < 4; ++k) {
+                    const int32_t r = min(rc + 1 + 64 * k + lane, nA - 1);
+                    pst[k] = apre[r];
+                    pab[k] = abase[r];
+                }
                 for (int32_t t = wid; t < ntile; t += NW) {
                     const int32_t t0 = t * WT;
                     const int32_t len = min(WT, W - t0);
                     const int32_t tn = t + NW;
                     const int32_t rcn = tn < ntile ? tf[tn] : 0;
-                    // rows that start inside the tile: mark their first
-                    // entry (256 rows per step, loads first)
+                    // the base of the row starting at each entry, kNoStart
+                    // elsewhere (256 rows per step, loads first)
+                    {
+                        int4* o4 = reinterpret_cast<int4*>(own + lane * IT);
+#pragma unroll
+                        for (int k = 0; k < IT / 4; ++k)
+                            o4[k] = make_int4(kNoStart, kNoStart, kNoStart, kNoStart);
+                    }
+                    wave_sync();
                     for (int32_t r0 = rc + 1; r0 < nA; r0 += 256) {
-                        int32_t st[4];
+                        int32_t st[4], sb[4];
                         if (r0 == rc + 1) {
 #pragma unroll
-                            for (int k = 0; k < 4; ++k) st[k] = pst[k];
+                            for (int k = 0; k < 4; ++k) {
+                                st[k] = pst[k];
+                                sb[k] = pab[k];
+                            }
                         } else {
 #pragma unroll
-                            for (int k = 0; k < 4; ++k)
-                                st[k] = apre[min(r0 + 64 * k + lane, nA - 1)];
+                            for (int k = 0; k < 4; ++k) {
+                                const int32_t r = min(r0 + 64 * k + lane, nA - 1);
+                                st[k] = apre[r];
+                                sb[k] = abase[r];
+                            }
                         }
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
                             const int32_t r = r0 + 64 * k + lane;
-                            if (r < nA && st[k] < t0 + len) own[st[k] - t0] = r;
+                            if (r < nA && st[k] < t0 + len) own[st[k] - t0] = sb[k];
                         }
                         // rows start in increasing order: stop once the last
                         // row of this step lies beyond the tile
                         if (__shfl(st[3], 63, 64) >= t0 + len) break;
                     }
                     wave_sync();
-                    // owner of every entry: running max over the marks (rows
-                    // start at increasing offsets; older marks are <= rc)
-                    int32_t row[IT];
-                    int32_t run = rc;
+                    // base of every entry: the last row start at or before it
+                    // (forward fill; the tile's first row, rc, starts before
+                    // the tile and has base bc)
                     {
-                        const int4* o4 = reinterpret_cast<const int4*>(own + lane * IT);
+                        int4* o4 = reinterpret_cast<int4*>(own + lane * IT);
+                        int32_t bv[IT];
 #pragma unroll
                         for (int k = 0; k < IT / 4; ++k) {
                             const int4 x = o4[k];
-                            row[4 * k + 0] = run = max(run, x.x);
-                            row[4 * k + 1] = run = max(run, x.y);
-                            row[4 * k + 2] = run = max(run, x.z);
-                            row[4 * k + 3] = run = max(run, x.w);
+                            bv[4 * k + 0] = x.x;
+                            bv[4 * k + 1] = x.y;
+                            bv[4 * k + 2] = x.z;
+                            bv[4 * k + 3] = x.w;
                         }
-                    }
-                    const int32_t inc = wave_incl_max(run);
-                    int32_t carry = __shfl_up(inc, 1, 64);
-                    if (lane == 0) carry = rc;
-                    wave_sync();
-                    {
-                        int4* o4 = reinterpret_cast<int4*>(own + lane * IT);
+                        int32_t last = kNoStart;
+#pragma unroll
+                        for (int i = 0; i < IT; ++i) last = bv[i] != kNoStart ? bv[i] : last;
+                        // the last start of the lanes before this one
+                        int32_t carry = last;
+#pragma unroll
+                        for (int off = 1; off < 64; off <<= 1) {
+                            const int32_t y = __shfl_up(carry, off, 64);
+                            if (lane >= off && carry == kNoStart) carry = y;
+                        }
+                        carry = __shfl_up(carry, 1, 64);
+                        if (lane == 0 || carry == kNoStart) carry = bc;
+#pragma unroll
+                        for (int i = 0; i < IT; ++i) {
+                            if (bv[i] == kNoStart) bv[i] = carry;
+                            carry = bv[i];
+                        }
+                        wave_sync();
 #pragma unroll
                         for (int k = 0; k < IT / 4; ++k)
-                            o4[k] = make_int4(max(row[4 * k + 0], carry), max(row[4 * k + 1], carry),
-                                              max(row[4 * k + 2], carry), max(row[4 * k + 3], carry));
+                            o4[k] = make_int4(bv[4 * k + 0], bv[4 * k + 1], bv[4 * k + 2],
+                                              bv[4 * k + 3]);
                     }
                     wave_sync();
                     // neighbour ids, consecutive lanes on consecutive
@@ -375,11 +405,9 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
                     // lanes past the tile end re-read its last entry.
                     int32_t u[IT];
                     {
-                        int32_t rw[IT], ab[IT];
+                        int32_t ab[IT];
 #pragma unroll
-                        for (int j = 0; j < IT; ++j) rw[j] = own[min(j * 64 + lane, len - 1)];
-#pragma unroll
-                        for (int j = 0; j < IT; ++j) ab[j] = abase[rw[j]];
+                        for (int j = 0; j < IT; ++j) ab[j] = own[min(j * 64 + lane, len - 1)];
 #pragma unroll
                         for (int j = 0; j < IT; ++j)
                             u[j] = __builtin_nontemporal_load(ci + ab[j] + t0 +
@@ -387,9 +415,13 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
                     }
                     // next tile's row starts, in flight during this tile's
                     // state lookups and decrements
+                    bc = abase[rcn];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        pst[k] = apre[min(rcn + 1 + 64 * k + lane, nA - 1)];
+                    for (int k = 0; k < 4; ++k) {
+                        const int32_t r = min(rcn + 1 + 64 * k + lane, nA - 1);
+                        pst[k] = apre[r];
+                        pab[k] = abase[r];
+                    }
                     // states: the LDS word for ids below cap, the removal
                     // pass (device memory) above
                     uint32_t sv[IT];
