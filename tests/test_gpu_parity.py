@@ -123,6 +123,14 @@ def test_launch_shape_does_not_change_results(dsg, launch):
     check(g, (1, 10), launch=launch)
 
 
+def test_walk_grid_above_partial_slots(dsg):
+    # R-MAT scale 20 has more than 7000 walk tiles in its first passes; the
+    # library keeps one partial count per walk workgroup and uses at most
+    # 4096 workgroups, so a larger requested grid is clamped, not an error
+    check(_rmat20(), (1, 10), launch={"walk_grid": 6000})
+    check(_rmat20(), (1, 10), launch={"walk_grid": 4096, "mark_grid": 3})
+
+
 def test_relabel_permutes_result(dsg):
     g = inputs.chung_lu(40_000, 16, 2.3, 13)
     perm = np.random.default_rng(3).permutation(g.n)
