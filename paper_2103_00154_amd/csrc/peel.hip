@@ -614,12 +614,13 @@ __device__ void finish_pass(const Work& w, int32_t* s_flag, int32_t* red) {
         for (int32_t b = threadIdx.x; b < nb; b += kBlock)
             w.bin_items[b] = make_int2((int)(b * ipb), total_a <= cap_a ? (int)ipb : 0);
         if (threadIdx.x == 0) {
-            // lanes per (tile, bin) run in k_apply: one batch of loads per
-            // lane covers a mean run, so many runs are in flight per workgroup
+            // lanes per (tile, bin) run in k_apply: about four batches of
+            // loads per lane cover a mean run, so a wave counts several runs
+            // at once (at least 8 lanes per run)
             const int64_t runs = std::max<int64_t>(1, ntiles * nb);
-            const int64_t mean = (int64_t)atomic_load_u64(&st->cross) / runs;
-            int32_t lanes = 4;
-            while (lanes < 64 && kApplyBatch * lanes < mean) lanes *= 2;
+            const int64_t mean = (int64_t)st->cross / runs;
+            int32_t lanes = 8;
+            while (lanes < 64 && kApplyBatch * lanes * 4 < mean) lanes *= 2;
             st->apply_lanes = lanes;
             // lanes per rank in k_reduce: about four partial rows per lane
             int32_t rl = 1;
