@@ -215,8 +215,4 @@ __device__ inline int32_t block_excl_max(int32_t x, int32_t* red, int32_t lo) {
     return max(before, excl_in_wave);
 }
 
-__device__ inline unsigned long long atomic_load_u64(const unsigned long long* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 }  // namespace dsg
