@@ -185,6 +185,55 @@ __device__ inline T block_sum(T x, T* red) {
     return all;
 }
 
+// K block-wide sums at once (every thread gets all K).  `red` holds
+// K * kWaves elements of LDS.  Two barriers.
+template <int K>
+__device__ inline void block_sum_k(uint32_t (&x)[K], uint32_t* red) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] = wave_sum(x[k]);
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[k * kWaves + wave_id()] = x[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        uint32_t all = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) all += red[k * kWaves + w];
+        x[k] = all;
+    }
+    __syncthreads();
+}
+
+// K block-wide exclusive sums at once: x[k] becomes the sum over the
+// threads before this one, total[k] the block sum.  `red` holds K * kWaves
+// elements of LDS.  Two barriers.
+template <int K>
+__device__ inline void block_excl_sum_k(uint32_t (&x)[K], uint32_t* red, uint32_t (&total)[K]) {
+    uint32_t incl[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) incl[k] = wave_incl_sum(x[k]);
+    if (lane_id() == 63) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[k * kWaves + wave_id()] = incl[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        uint32_t before = 0, all = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t v = red[k * kWaves + w];
+            before += (w < wave_id()) ? v : 0u;
+            all += v;
+        }
+        total[k] = all;
+        x[k] = before + incl[k] - x[k];
+    }
+    __syncthreads();
+}
+
 // Block-wide minimum of unsigned values, returned to every thread.  Two
 // barriers.
 template <int NW = kWaves>

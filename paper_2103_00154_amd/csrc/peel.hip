@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
     // what removed_at records: the pass, or in core mode the level (which is
     // the core number of every vertex removed at that level)
     const int32_t rv = st->core_mode ? T : pass;
-    __shared__ uint32_t red[kWaves];
+    __shared__ uint32_t red[5 * kWaves];
 
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t base = t * kMarkTile + (int64_t)threadIdx.x * kMarkItems;
@@ -305,15 +305,14 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
                 w.dir[wbase >> 5].x = valid & ~gone;
             }
         }
-        const uint32_t tA = block_sum(cA, red);
-        const uint32_t tL = block_sum(cL, red);
-        const uint32_t tE = block_sum(cE, red);
-        const uint32_t tDr = block_sum(cDr, red);
-        const uint32_t tDs = block_sum(cDs, red);
-        const uint32_t tMin = block_min(dmin, red);
+        // the five tile sums in one reduction; the least survivor degree
+        // (core levels only) in a second one
+        uint32_t sums[5] = {cA, cL, cE, cDr, cDs};
+        block_sum_k<5>(sums, red);
+        const uint32_t tMin = st->core_mode ? block_min(dmin, red) : 0xFFFFFFFFu;
         if (threadIdx.x == 0) {
-            w.tiles[2 * t] = make_int4((int)tA, (int)tL, (int)tE, (int)tDr);
-            w.tiles[2 * t + 1] = make_int4((int)tDs, (int)tMin, 0, 0);
+            w.tiles[2 * t] = make_int4((int)sums[0], (int)sums[1], (int)sums[2], (int)sums[3]);
+            w.tiles[2 * t + 1] = make_int4((int)sums[4], (int)tMin, 0, 0);
         }
     }
 }
@@ -417,7 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
     // a pass that leaves no survivor walks nothing: no walk tiles to mark
     const int64_t wcap = st->nL > 0 ? walk_cap : 0;
     const int64_t ntiles = (S + kMarkTile - 1) / kMarkTile;
-    __shared__ uint32_t red[kWaves];
+    __shared__ uint32_t red[3 * kWaves];
 
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t base = t * kMarkTile + (int64_t)threadIdx.x * kMarkItems;
@@ -477,10 +476,9 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
         int32_t prev = -1;
         if (base > 0 && base - 1 < S) prev = lin ? lin[base - 1] : (int32_t)(base - 1);
 
-        uint32_t tot_packed, tot_e, tot_ds;
-        const uint32_t ex_packed = block_excl_sum(cA | (cL << 16), red, &tot_packed);
-        const uint32_t ex_e = block_excl_sum(cE, red, &tot_e);
-        const uint32_t ex_ds = block_excl_sum(cDs, red, &tot_ds);
+        uint32_t ex[3] = {cA | (cL << 16), cE, cDs}, tot[3];
+        block_excl_sum_k<3>(ex, red, tot);
+        const uint32_t ex_packed = ex[0], ex_e = ex[1], ex_ds = ex[2];
         const int4 tp = w.tiles[2 * t];
         const int4 tq = w.tiles[2 * t + 1];
         int64_t pA = (int64_t)tp.x + (ex_packed & 0xFFFFu);
