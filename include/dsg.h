@@ -282,8 +282,9 @@ typedef struct {
     int32_t reserved;
 } dsg_batch_result;
 
-/* Launch shape of the persistent kernel; 0 selects the library default.
- * Results never depend on these. */
+/* Launch shape of the persistent kernel; 0 selects the library default
+ * (512 threads, one workgroup per CU, 8 entries per lane).  Results never
+ * depend on these. */
 typedef struct {
     int32_t block;         /* threads per workgroup: 256, 512 or 1024        */
     int32_t blocks_per_cu; /* workgroups resident per CU (LDS is split): 1..8 */

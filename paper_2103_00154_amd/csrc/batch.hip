@@ -667,7 +667,7 @@ int32_t dsg_batch_prepare(const dsg_batch_graph* graphs, int32_t count, int64_t 
     if (row_ptr_len < 0 || col_idx_len < 0 || out_len < 0) return DSG_EINVAL;
     if (!workspace || ((uintptr_t)workspace & 255u)) return DSG_EINVAL;
 
-    int32_t block = 512, bpc = 1, items = 16, grid = 0;
+    int32_t block = 512, bpc = 1, items = 8, grid = 0;
     if (launch) {
         if (launch->block) block = launch->block;
         if (launch->blocks_per_cu) bpc = launch->blocks_per_cu;
