@@ -174,3 +174,24 @@ def test_hip_graph_capture_and_replay():
         torch.cuda.synchronize()
         assert dsg.Batch.results(other) == [dict(g, best_size=0) for g in got]
         say(f"replay {rep} ok")
+
+
+def _with_clique(n_extra, extra_edges, k=60):
+    """A k-clique on ids 0..k-1 plus `extra_edges` on ids k..k+n_extra-1."""
+    core = [(i, j) for i in range(k) for j in range(i + 1, k)]
+    return inputs.from_edges(k + n_extra, core + [(k + a, k + b) for a, b in extra_edges])
+
+
+def test_wave_tiles_over_many_short_rows():
+    # the clique survives the first pass while the pendant structures fail
+    # with rows of length 1, so one wave tile spans hundreds of walked rows:
+    # more than the 256 whose starts and bases are loaded one tile ahead
+    matching = _with_clique(20_000, [(2 * i, 2 * i + 1) for i in range(10_000)])
+    stars = _with_clique(40_000, [(4 * i, 4 * i + j) for i in range(10_000) for j in (1, 2, 3)])
+    paths = _with_clique(30_000, [(i, i + 1) for i in range(29_999) if i % 3 != 2])
+    b = inputs.concat([matching, stars, paths, inputs.clique(40)])
+    want = oracle_all(b)
+    assert all(o.passes >= 2 for o in want[:3])
+    for launch in (None, {"block": 256, "walk_items": 16}, {"block": 1024, "walk_items": 4},
+                   {"block": 512, "walk_items": 4}):
+        check_batch(b, launch=launch, want=want)

@@ -131,6 +131,22 @@ def test_walk_grid_above_partial_slots(dsg):
     check(_rmat20(), (1, 10), launch={"walk_grid": 4096, "mark_grid": 3})
 
 
+@pytest.mark.parametrize("shape", ["matching", "stars", "paths"])
+def test_walk_tiles_over_thousands_of_rows(dsg, shape):
+    # a 60-clique survives the first pass while thousands of pendant rows of
+    # length 1 fail: one 4096-entry walk tile spans up to 4096 rows, so the
+    # row table takes several rounds and the owner scan covers every entry
+    k = 60
+    extra = {"matching": (20_000, [(2 * i, 2 * i + 1) for i in range(10_000)]),
+             "stars": (40_000, [(4 * i, 4 * i + j) for i in range(10_000) for j in (1, 2, 3)]),
+             "paths": (30_000, [(i, i + 1) for i in range(29_999) if i % 3 != 2])}[shape]
+    edges = [(i, j) for i in range(k) for j in range(i + 1, k)]
+    edges += [(k + a, k + b) for a, b in extra[1]]
+    g = inputs.from_edges(k + extra[0], edges)
+    for eps in ((1, 10), (0, 1)):
+        check(g, eps)
+
+
 def test_relabel_permutes_result(dsg):
     g = inputs.chung_lu(40_000, 16, 2.3, 13)
     perm = np.random.default_rng(3).permutation(g.n)
