@@ -104,8 +104,9 @@ typedef struct {
 typedef struct {
     double ms_init;     /* init kernels */
     double ms_mark;     /* mark-count + tile-scan + mark-scatter kernels */
-    double ms_walk;     /* neighbour-walk kernels */
-    double ms_apply;    /* degree-update kernels (per-bin LDS counts) */
+    double ms_walk;     /* neighbour-walk kernel */
+    double ms_apply;    /* pass completion and degree-update kernels (sum of the walk's
+                           partial counts, per-bin LDS counts, degree reduction) */
     double ms_extract;  /* extract kernels */
     double ms_total;    /* first launch to last kernel end */
     int32_t launches_walk;
@@ -126,9 +127,9 @@ const char* dsg_strerror(int32_t status);
 
 /* Bytes of device workspace dsg_peel needs for a graph with n vertices and
  * m undirected edges; 0 for invalid sizes.  About 28 n + 4 m bytes, plus
- * 2 * ceil(2m / 2048) * (min(n / 32768, 1024) + 2) bytes of per-tile bin
- * offsets and min(n, 32768) * 4 bytes per degree-update work item (at most
- * n / 32768 + 514 items). */
+ * 2 * (ceil(2m / 4096) + 1) * (min(ceil(n / 32768) + 1, 1024) + 1) bytes of
+ * per-tile bin offsets, min(n, 32768) * 4 bytes per degree-update work item
+ * (at most n / 32768 + 514 items) and about 40 KB of fixed tables. */
 size_t dsg_workspace_bytes(int64_t n, int64_t m);
 
 /*
