@@ -149,3 +149,40 @@ def test_batch_with_col_idx_offsets_beyond_int32():
             assert r["best_size"] == n
     del rp_all, ci_all, best, rem, plan, res
     torch.cuda.empty_cache()
+
+
+def cbds_expected(n_side: int):
+    """CBDS-P of the bridged cliques: core number 32 for the 32-clique part
+    (31 clique mates and a bridge), 63 for the 64-clique part; the cores of
+    order 33..63 are the 64-clique part (density 63/2 > 24), so K = 33; the
+    32-clique vertices are eligible (32 > 31.5) but have one neighbour in the
+    core, so none is legitimate."""
+    return dict(num=63 * n_side // 2, den=n_side, core_num=63 * n_side // 2, core_den=n_side,
+                K=33, kmax=63, n_eligible=n_side, n_legit=0)
+
+
+def check_cbds(r, n_side):
+    import torch
+    want = cbds_expected(n_side)
+    got = {k: getattr(r, k) for k in want}
+    assert got == want, (got, want)
+    ids = torch.arange(n_side, dtype=torch.int32, device=r.best.device)
+    assert r.best.numel() == n_side and bool((r.best == ids).all())
+    assert bool((r.core[:n_side] == 63).all()) and bool((r.core[n_side:] == 32).all())
+
+
+def test_cbds_closed_form_small_and_just_below_int32_limit():
+    import torch
+    from paper_2103_00154_amd import dsg
+    n_side = 64 * 40
+    rp, ci = bridged_cliques(n_side, "cpu")
+    g = inputs.Graph(2 * n_side, ci.numel() // 2, rp.numpy(), ci.numpy(), name="bridged")
+    o = oracle.cbds(g)
+    want = cbds_expected(n_side)
+    assert {k: getattr(o, k) for k in want} == want
+    check_cbds(dsg.cbds(rp.cuda(), ci.cuda(), core=True), n_side)
+    say(f"CBDS-P on bridged cliques with 2m = {96 * N_MAX}")
+    rp, ci = bridged_cliques(N_MAX, "cuda")
+    check_cbds(dsg.cbds(rp, ci, core=True), N_MAX)
+    del rp, ci
+    torch.cuda.empty_cache()
