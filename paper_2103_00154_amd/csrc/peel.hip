@@ -420,6 +420,12 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
 
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t base = t * kMarkTile + (int64_t)threadIdx.x * kMarkItems;
+        // the tile's prefix record and the element before this thread's
+        // first one are loaded with the data, not after the block scan
+        const int4 tp = w.tiles[2 * t];
+        const int4 tq = w.tiles[2 * t + 1];
+        int32_t prev = -1;
+        if (base > 0 && base - 1 < S) prev = lin ? lin[base - 1] : (int32_t)(base - 1);
         int32_t vv[kMarkItems];
         int32_t dd[kMarkItems];
         int32_t ll[kMarkItems];
@@ -472,15 +478,11 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
                 cDs += (uint32_t)dd[j];
             }
         }
-        // the element before this thread's first one decides word leadership
-        int32_t prev = -1;
-        if (base > 0 && base - 1 < S) prev = lin ? lin[base - 1] : (int32_t)(base - 1);
-
+        // the element before this thread's first one (prev) decides word
+        // leadership
         uint32_t ex[3] = {cA | (cL << 16), cE, cDs}, tot[3];
         block_excl_sum_k<3>(ex, red, tot);
         const uint32_t ex_packed = ex[0], ex_e = ex[1], ex_ds = ex[2];
-        const int4 tp = w.tiles[2 * t];
-        const int4 tq = w.tiles[2 * t + 1];
         int64_t pA = (int64_t)tp.x + (ex_packed & 0xFFFFu);
         int64_t pL = (int64_t)tp.y + (ex_packed >> 16);
         int64_t pE = (int64_t)(uint32_t)tp.z + ex_e;
@@ -587,7 +589,10 @@ __device__ void finish_pass(const Work& w, int32_t* s_flag, int32_t* red) {
         *s_flag = keep;
     }
     __syncthreads();
-    if (!*s_flag) {
+    // no records (a pass that removed nothing, or whose failures had no
+    // surviving neighbour): every partial count would be zero, so the apply
+    // kernels have nothing to do
+    if (!*s_flag || st->cross == 0) {
         if (threadIdx.x == 0) st->n_items = 0;
         return;
     }
