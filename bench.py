@@ -85,6 +85,27 @@ def stored_traffic(workload: str, launches: int):
     return rec.get("bytes_per_launch")
 
 
+def measure_copy_gbs(torch, dev, nbytes: int = 4 << 30, reps: int = 5) -> float:
+    """Measured copy ceiling of this GPU: a device-to-device copy of `nbytes`
+    (hipMemcpyAsync), bytes read plus bytes written per second, median of
+    `reps` copies timed with HIP events."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        z = torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        z.record()
+        z.synchronize()
+        times.append(a.elapsed_time(z))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (statistics.median(times) * 1e-3) / 1e9
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +244,8 @@ def main() -> int:
     # per vertex (row_ptr pair, removal pass, extraction read, init writes)
     path_bytes = (8 * walked + 8 * cross + 12 * live + 12 * walk_list) / args.steps + 24 * g.n
     path_gbs = path_bytes / (ms_per_step * 1e-3) / 1e9
+    copy_gbs = measure_copy_gbs(torch, dev)
+    log(f"device-to-device copy: {copy_gbs:.0f} GB/s (bytes read + written)")
 
     cpu = None
     parity = None
@@ -278,7 +301,9 @@ def main() -> int:
                      "traffic": traffic, "kernel": "k_walk",
                      "launches_per_step": walk_launches // args.steps,
                      "ms_per_launch": round(per_launch_ms, 4),
-                     "alg_bytes_per_launch": int(per_launch_bytes)},
+                     "alg_bytes_per_launch": int(per_launch_bytes),
+                     "stream_copy": round(copy_gbs, 1),
+                     "frac_of_stream_copy": round(achieved / copy_gbs, 4)},
         "kernel_ms_per_step": {"instrumented_step": round(ms_profiled, 4),
                                "walk": round(walk_ms / args.steps, 4),
                                "apply": round(apply_ms / args.steps, 4),
