@@ -133,11 +133,16 @@ class Server:
 
     ``big_vertices``: requests with more vertices go to the single-graph lane
     (None: the LDS vertex capacity of the batch kernel's launch shape; 0 or a
-    huge value disables the lane); ``big_lanes`` worker threads serve it."""
+    huge value disables the lane); ``big_lanes`` worker threads serve it.
+    ``reserve_cus``: CUs kept free of batch workgroups for the single-graph
+    lane (None: a quarter of the CUs while the lane is on).  A persistent
+    batch workgroup holds most of its CU's LDS, so without a reserve a loaded
+    server leaves the lane's kernels no CU to run on; each micro-batch's grid
+    is capped at (CUs - reserve) / streams workgroups."""
 
     def __init__(self, budget_bytes: int, *, streams: int = 4, max_batch: int = 512,
                  launch: dict | None = None, device=None, big_vertices: int | None = None,
-                 big_lanes: int = 1):
+                 big_lanes: int = 2, reserve_cus: int | None = None):
         import torch
         self.device = torch.device(device or "cuda")
         if self.device.index is None:
@@ -148,6 +153,10 @@ class Server:
         if big_vertices is None:
             big_vertices = _lds_vertices(launch, self.device)
         self.big_vertices = big_vertices
+        cus = torch.cuda.get_device_properties(self.device).multi_processor_count
+        if reserve_cus is None:
+            reserve_cus = cus // 4 if big_vertices else 0
+        self.batch_grid = max(1, (cus - min(reserve_cus, cus - 1)) // max(streams, 1))
         self.big_waiting: deque[Request] = deque()
         self.big_busy = 0
         self.big_done = 0
@@ -340,7 +349,9 @@ class Server:
         tab, count = dsg.batch_table(n_arr, m_arr, rp_off, ci_off, out, eps)
         ws = self.buf[ws_off:ws_off + ws_bytes]
         with torch.cuda.stream(s):
-            plan = dsg.Batch(tab, count, ints.numel(), ints.numel(), sum_n, launch=self.launch,
+            launch = dict(self.launch or {})
+            launch["grid"] = min(count, self.batch_grid)
+            plan = dsg.Batch(tab, count, ints.numel(), ints.numel(), sum_n, launch=launch,
                              workspace=ws, device=self.device, stream=s)
             for o, r in zip(csr_off, take):
                 ints[o // 4:o // 4 + r.graph.csr.numel()].copy_(r.graph.csr, non_blocking=True)
