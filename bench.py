@@ -129,6 +129,7 @@ def main() -> int:
     ap.add_argument("--serve-qps", type=float, default=2000.0)
     ap.add_argument("--serve-requests", type=int, default=3000)
     ap.add_argument("--serve-pool", type=int, default=256)
+    ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES bytes device-to-device once (reference kernel for "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE scaling) and exit")
@@ -454,12 +455,12 @@ def bench_serve(args, torch) -> dict:
     log(f"serve: pool of {len(graphs)} graphs (n median {int(np.median(b.n))}, max "
         f"{int(b.n.max())}; m total {int(b.m.sum())}) built in {time.time() - t0:.1f}s")
     budget = 16 << 30
-    srv = serve.Server(budget, streams=4, max_batch=256)
+    srv = serve.Server(budget, streams=args.serve_streams, max_batch=256)
     # warm-up: a short stream, not timed
     serve.run_load(srv, hg, eps_choices, qps=args.serve_qps, count=64, seed=99)
     srv.close()
     del srv
-    srv = serve.Server(budget, streams=4, max_batch=256)
+    srv = serve.Server(budget, streams=args.serve_streams, max_batch=256)
     reqs = serve.run_load(srv, hg, eps_choices, qps=args.serve_qps, count=args.serve_requests,
                           seed=7)
     srv.close()
@@ -467,7 +468,8 @@ def bench_serve(args, torch) -> dict:
     st = serve.latency_stats(reqs)
     log(f"serve: {st}; {srv.batches} micro-batches (mean {np.mean(srv.batch_sizes):.1f} "
         f"requests), up to {srv.max_in_flight} in flight, {srv.big_done} requests above "
-        f"{srv.big_vertices} vertices in the single-graph lane, arena peak "
+        f"{srv.big_vertices} vertices in the single-graph lane ({srv.overflowed} more in "
+        f"batches of their own while the lane was busy), arena peak "
         f"{srv.arena.peak >> 20} MiB")
     # every (graph, eps) pair that was served, peeled alone
     same = all(r.result["status"] == 0 for r in reqs)
@@ -491,10 +493,11 @@ def bench_serve(args, torch) -> dict:
                      f"lognormal (median 20000, sigma 1, capped at 2000000), avg degree U[8, 64], "
                      f"gamma U[2.1, 2.8], eps from {{1/100, 1/10, 1/2}}; pool of "
                      f"{len(graphs)} graphs, each request uploads its CSR"),
-        "offered_qps": args.serve_qps, "budget_bytes": budget, "streams": 4,
+        "offered_qps": args.serve_qps, "budget_bytes": budget, "streams": args.serve_streams,
         "micro_batches": srv.batches, "mean_batch": round(float(np.mean(srv.batch_sizes)), 2),
         "max_in_flight": srv.max_in_flight, "arena_peak_bytes": srv.arena.peak,
-        "single_graph_lane": {"above_vertices": srv.big_vertices, "requests": srv.big_done},
+        "single_graph_lane": {"above_vertices": srv.big_vertices, "requests": srv.big_done,
+                              "overflowed_to_batches": srv.overflowed},
         "parity": parity})
 
 

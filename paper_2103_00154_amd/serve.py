@@ -117,6 +117,7 @@ class _MicroBatch:
     best_host: object
     best_off: list = field(default_factory=list)
     res_dev: object = None
+    solo: bool = False
 
 
 def footprint(n: int, m: int) -> int:
@@ -138,11 +139,15 @@ class Server:
     lane (None: a quarter of the CUs while the lane is on).  A persistent
     batch workgroup holds most of its CU's LDS, so without a reserve a loaded
     server leaves the lane's kernels no CU to run on; each micro-batch's grid
-    is capped at (CUs - reserve) / streams workgroups."""
+    is capped at (CUs - reserve) / streams workgroups.
+    ``overflow``: when the lane has a backlog (twice as many requests waiting
+    as it has workers), a large request goes to the batch kernel instead, in
+    a micro-batch of its own (so that its long run on one CU delays no other
+    request's result)."""
 
     def __init__(self, budget_bytes: int, *, streams: int = 4, max_batch: int = 512,
                  launch: dict | None = None, device=None, big_vertices: int | None = None,
-                 big_lanes: int = 2, reserve_cus: int | None = None):
+                 big_lanes: int = 2, reserve_cus: int | None = None, overflow: bool = True):
         import torch
         self.device = torch.device(device or "cuda")
         if self.device.index is None:
@@ -171,6 +176,9 @@ class Server:
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self.busy = [None] * streams
         self.waiting: deque[Request] = deque()
+        self.solo: deque[Request] = deque()   # large requests overflowing into batches
+        self.overflow = overflow
+        self.overflowed = 0
         self.max_batch = max_batch
         self.launch = launch
         self.completed: list[Request] = []
@@ -190,8 +198,14 @@ class Server:
             raise ValueError(f"request {req.rid} needs more memory than the whole budget")
         if big:
             with self._cv:
-                self.big_waiting.append(req)
-                self._cv.notify()
+                backlog = len(self.big_waiting) >= 2 * len(self._lanes)
+                if not (self.overflow and backlog and
+                        footprint(req.graph.n, req.graph.m) <= self.arena.size):
+                    self.big_waiting.append(req)
+                    self._cv.notify()
+                    return
+            self.solo.append(req)
+            self.overflowed += 1
         else:
             self.waiting.append(req)
 
@@ -199,7 +213,8 @@ class Server:
     def idle(self) -> bool:
         with self.lock:
             big_idle = not self.big_waiting and self.big_busy == 0
-        return big_idle and not self.waiting and all(b is None for b in self.busy)
+        return (big_idle and not self.waiting and not self.solo
+                and all(b is None for b in self.busy))
 
     def close(self) -> None:
         with self._cv:
@@ -302,18 +317,19 @@ class Server:
             got.append((off, nb))
         return got
 
-    def _launch(self, k: int) -> None:
+    def _launch(self, k: int, queue=None) -> None:
         with self.lock:
-            self._launch_locked(k)
+            self._launch_locked(k, self.waiting if queue is None else queue,
+                                self.max_batch if queue is None else 1)
 
-    def _launch_locked(self, k: int) -> None:
+    def _launch_locked(self, k: int, queue, max_batch: int) -> None:
         import torch
         take, allocs = [], []
         # admit in arrival order while the request's CSR and the batch's
         # shared regions (workspace, output slots) fit; the head request
         # waits for memory when it does not
-        while self.waiting and len(take) < self.max_batch:
-            rq = self.waiting[0]
+        while queue and len(take) < max_batch:
+            rq = queue[0]
             nb = 4 * (rq.graph.n + 1 + 2 * rq.graph.m)
             off = self.arena.alloc(nb)
             if off is None:
@@ -325,7 +341,7 @@ class Server:
             for o, b in trial:
                 self.arena.free(o, b)
             allocs.append((off, nb))
-            take.append(self.waiting.popleft())
+            take.append(queue.popleft())
         if not take:
             return
         csr_off = [o for o, _ in allocs]
@@ -364,7 +380,8 @@ class Server:
             best_host.copy_(best, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
-        self.busy[k] = _MicroBatch(take, s, ev, allocs, res_host, best_host, list(out), res)
+        self.busy[k] = _MicroBatch(take, s, ev, allocs, res_host, best_host, list(out), res,
+                                   solo=max_batch == 1)
         self.batches += 1
         self.batch_sizes.append(len(take))
         self.max_in_flight = max(self.max_in_flight, sum(b is not None for b in self.busy))
@@ -374,8 +391,15 @@ class Server:
         if self.error is not None:
             raise RuntimeError("single-graph lane failed") from self.error
         self._reap()
+        # overflowing large requests use at most half of the streams
+        solo_cap = max(1, len(self.busy) // 2)
         for k in range(len(self.busy)):
-            if self.busy[k] is None and self.waiting:
+            if self.busy[k] is not None:
+                continue
+            solo_now = sum(1 for b in self.busy if b is not None and b.solo)
+            if self.solo and solo_now < solo_cap:
+                self._launch(k, self.solo)
+            elif self.waiting:
                 self._launch(k)
 
     def drain(self, timeout_s: float = 120.0) -> None:
