@@ -105,3 +105,25 @@ def test_request_larger_than_the_budget_is_refused():
     srv = serve.Server(64 * 1024, streams=1)
     with pytest.raises(ValueError):
         srv.submit(serve.Request(0, serve.HostGraph.from_graph(g), (1, 10), 0.0))
+
+
+def test_large_requests_overflow_into_batches_when_the_lane_is_backed_up():
+    import torch
+    from paper_2103_00154_amd import serve
+    # only graphs larger than the LDS vertex state, all arriving at once, one
+    # lane worker: the lane's queue backs up and later requests overflow into
+    # micro-batches of their own on the batch kernel
+    graphs = [inputs.chung_lu(150_000, 16, 2.3, seed=81), inputs.erdos_renyi(100_000, 300_000, 82),
+              inputs.chung_lu(120_000, 24, 2.6, seed=83)]
+    alone = _alone(graphs)
+    hg = [serve.HostGraph.from_graph(g) for g in graphs]
+    srv = serve.Server(4 << 30, streams=4, max_batch=8, big_lanes=1)
+    assert all(g.n > srv.big_vertices for g in graphs)
+    reqs = serve.run_load(srv, hg, EPS, qps=1e6, count=24, seed=6)
+    srv.close()
+    torch.cuda.synchronize()
+    say(f"stats {serve.latency_stats(reqs)}; lane {srv.big_done}, overflowed {srv.overflowed}")
+    assert srv.overflowed > 0 and srv.big_done > 0
+    assert srv.overflowed + srv.big_done == 24
+    assert srv.arena.used == 0
+    _check(reqs, graphs, alone)
