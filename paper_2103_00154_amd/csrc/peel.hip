@@ -603,7 +603,11 @@ __device__ void finish_pass(const Work& w, int32_t* s_flag, int32_t* red) {
         // tiles; a bin's items are consecutive
         const int32_t cap_a = st->max_items;
         const int64_t ntiles = st->n_tiles_walk;
-        const int64_t ipb = std::max<int64_t>(1, std::min<int64_t>(ntiles, kTargetItems / nb));
+        // items per bin: with one or two bins, half as many items (fewer
+        // partial rows to write and reduce) measured faster; with more bins,
+        // the full count keeps every CU busy
+        const int64_t target = nb <= 2 ? kTargetItems / 2 : kTargetItems;
+        const int64_t ipb = std::max<int64_t>(1, std::min<int64_t>(ntiles, target / nb));
         const int64_t tpi = (ntiles + ipb - 1) / ipb;
         const int64_t total_a = (int64_t)nb * ipb;
         for (int64_t i = threadIdx.x; i < total_a && i < cap_a; i += kBlock) {
