@@ -186,3 +186,31 @@ def test_cbds_closed_form_small_and_just_below_int32_limit():
     check_cbds(dsg.cbds(rp, ci, core=True), N_MAX)
     del rp, ci
     torch.cuda.empty_cache()
+
+
+def test_star_with_a_hundred_million_leaves():
+    # ε = 1/10: threshold floor(2.2 * m / n) = 2, so every leaf fails in
+    # pass 1 and its one entry is a degree record for the hub (100 M records
+    # for a single survivor rank); the hub, left with degree 0, fails in
+    # pass 2; the whole graph (pass 0) stays the best.  CBDS-P: every core
+    # number is 1, C_0 = C_1 = G, so K = 0 and the result is G.
+    import torch
+    from paper_2103_00154_amd import dsg
+    leaves = 100_000_000
+    n = leaves + 1
+    rp = torch.cat([torch.zeros(1, dtype=torch.int64, device="cuda"),
+                    leaves + torch.arange(0, n, dtype=torch.int64, device="cuda")]).to(torch.int32)
+    ci = torch.cat([torch.arange(1, n, dtype=torch.int32, device="cuda"),
+                    torch.zeros(leaves, dtype=torch.int32, device="cuda")])
+    say(f"star with {leaves} leaves")
+    r = dsg.peel(rp, ci, (1, 10), removed_at=True, trace=True)
+    assert (r.passes, r.best_pass, r.num, r.den) == (2, 0, leaves, n)
+    assert r.best.numel() == n and bool((r.best == torch.arange(n, dtype=torch.int32, device="cuda")).all())
+    assert int(r.removed_at[0]) == 2 and bool((r.removed_at[1:] == 1).all())
+    t = r.trace[0]
+    assert (t["removed"], t["cross"], t["intra"], t["s_out"], t["e_out"]) == (leaves, leaves, 0, 1, 0)
+    c = dsg.cbds(rp, ci, core=True)
+    assert (c.num, c.den, c.K, c.kmax, c.n_legit) == (leaves, n, 0, 1, 0)
+    assert bool((c.core == 1).all()) and c.best.numel() == n
+    del rp, ci, r, c
+    torch.cuda.empty_cache()
