@@ -247,6 +247,14 @@ def main() -> int:
     path_gbs = path_bytes / (ms_per_step * 1e-3) / 1e9
     copy_gbs = measure_copy_gbs(torch, dev)
     log(f"device-to-device copy: {copy_gbs:.0f} GB/s (bytes read + written)")
+    # the per-pass trace of one more (untimed) peel
+    rt = dsg.peel(rp, ci, (num, den), best_ids=best, workspace=ws, trace=True)
+    trace_keys = ("s_in", "e_in", "thresh", "removed", "walked", "cross", "intra", "s_out", "e_out")
+    pass_trace = [{k: int(t[k]) for k in trace_keys} for t in rt.trace]
+    log("pass |S_in| T |A| walked cross intra |E_out|")
+    for k, t in enumerate(pass_trace):
+        log(f"{k + 1} {t['s_in']} {t['thresh']} {t['removed']} {t['walked']} {t['cross']} "
+            f"{t['intra']} {t['e_out']}")
 
     cpu = None
     parity = None
@@ -256,7 +264,7 @@ def main() -> int:
         o = None
         for _ in range(args.cpu_reps):
             c0 = time.perf_counter()
-            o = oracle.peel_graph(g, num, den, trace=False)
+            o = oracle.peel_graph(g, num, den, trace=True)
             times.append(time.perf_counter() - c0)
         t_cpu = statistics.median(times)
         cpu = {"value": round(g.m / t_cpu / 1e9, 4), "unit": "GTEPS", "cores": 1,
@@ -265,6 +273,11 @@ def main() -> int:
                          f"median of {args.cpu_reps} runs, {t_cpu:.2f} s each"}
         same = ((r.passes, r.best_pass, r.num, r.den) == (o.passes, o.best_pass, o.num, o.den)
                 and bool((best[:r.den].cpu().numpy() == o.best).all()))
+        # the per-pass trace too (the thresholds are clamped to int32 on the GPU)
+        same = same and len(pass_trace) == len(o.trace) and all(
+            all(a[k] == b[k] for k in ("s_in", "e_in", "removed", "cross", "intra", "s_out",
+                                       "e_out")) and a["thresh"] == min(b["thresh"], 2**31 - 1)
+            for a, b in zip(pass_trace, o.trace))
         parity = "exact" if same else "MISMATCH"
         log(f"oracle: {t_cpu:.2f} s ({g.m / t_cpu / 1e9:.3f} GTEPS), parity {parity}")
 
@@ -314,6 +327,7 @@ def main() -> int:
                           "alg_bytes_per_step": int(path_bytes)},
         "cpu_baseline": cpu,
         "parity": parity,
+        "pass_trace": pass_trace,
         "batch": batch,
         "serving": serving,
         "eps_sweep": eps_sweep,
