@@ -100,6 +100,7 @@ struct alignas(256) DevState {
     // level, and the next level is the least degree left
     int32_t core_mode;
     int32_t min_surv;     // least degree among this pass's survivors
+    int32_t jumped;       // 1: nothing failed at the level, this pass runs the next one
     uint32_t cb_nelig;    // CBDS-P phase 2: eligible outside vertices
     uint32_t cb_nlegit;   //   legitimate ones
     unsigned long long cb_sumlegit;  // their neighbours inside the core

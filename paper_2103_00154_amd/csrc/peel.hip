@@ -149,6 +149,7 @@ __global__ void k_init_state(Work w, const int32_t* __restrict__ rp, int64_t n, 
     st->best_pass = core_mode ? -1 : 0;
     st->core_mode = core_mode;
     st->min_surv = INT32_MAX;
+    st->jumped = 0;
     st->cb_nelig = st->cb_nlegit = 0;
     st->cb_sumlegit = st->cb_el = 0;
     st->done = 0;
@@ -205,7 +206,8 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
     const int64_t ntiles = (S + kMarkTile - 1) / kMarkTile;
     // what removed_at records: the pass, or in core mode the level (which is
     // the core number of every vertex removed at that level)
-    const int32_t rv = st->core_mode ? T : pass;
+    const bool core = st->core_mode != 0;
+    const int32_t rv = core ? T : pass;
     __shared__ uint32_t red[5 * kWaves];
 
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -234,14 +236,14 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
 #pragma unroll
             for (int j = 0; j < kMarkItems; ++j) ll[j] = dd[j];
         } else {
-            // row length of a failure with degree > 0 (pass 1: the degree
-            // itself); all row bounds are loaded before any is used (row 0
-            // stands in for the other entries)
+            // row length of a failure with degree > 0, and in core mode of
+            // every live vertex (pass 1: the degree itself); all row bounds
+            // are loaded before any is used (row 0 stands in for the others)
             int32_t rs[kMarkItems], re[kMarkItems];
             bool need[kMarkItems];
 #pragma unroll
             for (int j = 0; j < kMarkItems; ++j) {
-                need[j] = vv[j] >= 0 && dd[j] <= T && dd[j] > 0;
+                need[j] = vv[j] >= 0 && ((dd[j] <= T && dd[j] > 0) || core);
                 const int32_t x = need[j] ? vv[j] : 0;
                 rs[j] = rp[x];
                 re[j] = rp[x + 1];
@@ -309,10 +311,23 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
         // (core levels only) in a second one
         uint32_t sums[5] = {cA, cL, cE, cDr, cDs};
         block_sum_k<5>(sums, red);
-        const uint32_t tMin = st->core_mode ? block_min(dmin, red) : 0xFFFFFFFFu;
+        const uint32_t tMin = core ? block_min(dmin, red) : 0xFFFFFFFFu;
+        // core levels: the survivors of least degree and their row lengths
+        // (the failures of the next level if nothing fails at this one)
+        uint32_t least[2] = {0u, 0u};
+        if (core) {
+#pragma unroll
+            for (int j = 0; j < kMarkItems; ++j) {
+                if (vv[j] >= 0 && dd[j] > T && (uint32_t)dd[j] == tMin) {
+                    ++least[0];
+                    least[1] += (uint32_t)ll[j];
+                }
+            }
+            block_sum_k<2>(least, red);
+        }
         if (threadIdx.x == 0) {
             w.tiles[2 * t] = make_int4((int)sums[0], (int)sums[1], (int)sums[2], (int)sums[3]);
-            w.tiles[2 * t + 1] = make_int4((int)sums[4], (int)tMin, 0, 0);
+            w.tiles[2 * t + 1] = make_int4((int)sums[4], (int)tMin, (int)least[0], (int)least[1]);
         }
     }
 }
@@ -335,23 +350,56 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode,
     const int64_t per = (nt + kScanBlock - 1) / kScanBlock;
     const int64_t lo = std::min<int64_t>(nt, per * threadIdx.x);
     const int64_t hi = std::min<int64_t>(nt, lo + per);
-    int64_t a = 0, l = 0, e = 0, dr = 0, ds = 0;
-    uint32_t mn = 0xFFFFFFFFu;
-#pragma unroll 8
-    for (int64_t i = lo; i < hi; ++i) {
-        const int4 c = w.tiles[2 * i];
-        a += c.x;
-        l += c.y;
-        e += (uint32_t)c.z;
-        dr += (uint32_t)c.w;
-        if (mode == 0) {
-            const int4 q = w.tiles[2 * i + 1];
-            ds += (uint32_t)q.x;
-            mn = min(mn, (uint32_t)q.y);
-        }
-    }
     __shared__ int64_t red[kScanBlock / 64];
     __shared__ uint32_t redm[kScanBlock / 64];
+
+    // Core levels: when nothing fails at level T, the level has ended.  The
+    // next level is the least degree left, and the vertices failing there
+    // are exactly those of that degree, which every tile has counted (with
+    // their row lengths); the pass becomes the next level's first pass.
+    bool jump = false;
+    uint32_t jmin = 0xFFFFFFFFu;
+    if (mode == 0 && st->core_mode) {
+        int64_t l0 = 0;
+        uint32_t mn0 = 0xFFFFFFFFu;
+        for (int64_t i = lo; i < hi; ++i) {
+            l0 += w.tiles[2 * i].y;
+            mn0 = min(mn0, (uint32_t)w.tiles[2 * i + 1].y);
+        }
+        const int64_t tl0 = block_sum<int64_t, kScanBlock / 64>(l0, red);
+        jmin = block_min<kScanBlock / 64>(mn0, redm);
+        jump = items > 0 && tl0 == items;
+    }
+    int64_t a = 0, l = 0, e = 0, dr = 0, ds = 0;
+    uint32_t mn = 0xFFFFFFFFu;
+    if (!jump) {
+#pragma unroll 8
+        for (int64_t i = lo; i < hi; ++i) {
+            const int4 c = w.tiles[2 * i];
+            a += c.x;
+            l += c.y;
+            e += (uint32_t)c.z;
+            dr += (uint32_t)c.w;
+            if (mode == 0) {
+                const int4 q = w.tiles[2 * i + 1];
+                ds += (uint32_t)q.x;
+                mn = min(mn, (uint32_t)q.y);
+            }
+        }
+    } else {
+        // the next level's failures: the least-degree vertices of the tiles
+        // whose least degree is the global one
+        for (int64_t i = lo; i < hi; ++i) {
+            const int4 c = w.tiles[2 * i];
+            const int4 q = w.tiles[2 * i + 1];
+            const int64_t k = (uint32_t)q.y == jmin ? q.z : 0;
+            a += k;
+            l += c.y - k;
+            e += k ? (uint32_t)q.w : 0u;
+            dr += k * (int64_t)jmin;
+            ds += (uint32_t)q.x - k * (int64_t)jmin;
+        }
+    }
     const uint32_t tmin = block_min<kScanBlock / 64>(mn, redm);
     int64_t ta, tl, te, tds;
     int64_t pa = block_excl_sum<int64_t, kScanBlock / 64>(a, red, &ta);
@@ -363,24 +411,52 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode,
     const bool filt = mode == 0 && tl > 0 && tl <= kFiltBits;
     if (filt)
         for (int i = threadIdx.x; i < kFiltWords; i += kScanBlock) w.filt[i] = 0u;
+    if (!jump) {
 #pragma unroll 8
-    for (int64_t i = lo; i < hi; ++i) {
-        const int4 c = w.tiles[2 * i];
-        const int32_t cds = mode == 0 ? w.tiles[2 * i + 1].x : 0;
-        w.tiles[2 * i] = make_int4((int)pa, (int)pl, (int)pe, c.w);
-        w.tiles[2 * i + 1] = make_int4((int)pds, 0, 0, 0);
-        pa += c.x;
-        pl += c.y;
-        pe += (uint32_t)c.z;
-        pds += (uint32_t)cds;
+        for (int64_t i = lo; i < hi; ++i) {
+            const int4 c = w.tiles[2 * i];
+            const int32_t cds = mode == 0 ? w.tiles[2 * i + 1].x : 0;
+            w.tiles[2 * i] = make_int4((int)pa, (int)pl, (int)pe, c.w);
+            w.tiles[2 * i + 1] = make_int4((int)pds, 0, 0, 0);
+            pa += c.x;
+            pl += c.y;
+            pe += (uint32_t)c.z;
+            pds += (uint32_t)cds;
+        }
+    } else {
+        for (int64_t i = lo; i < hi; ++i) {
+            const int4 c = w.tiles[2 * i];
+            const int4 q = w.tiles[2 * i + 1];
+            const int64_t k = (uint32_t)q.y == jmin ? q.z : 0;
+            w.tiles[2 * i] = make_int4((int)pa, (int)pl, (int)pe, c.w);
+            w.tiles[2 * i + 1] = make_int4((int)pds, 0, 0, 0);
+            pa += k;
+            pl += c.y - k;
+            pe += k ? (uint32_t)q.w : 0u;
+            pds += (uint32_t)q.x - k * (int64_t)jmin;
+        }
     }
     if (threadIdx.x == 0) {
         if (mode == 0) {
+            if (jump) {
+                // what is left is the (T+1)-core: compare it with the best
+                // (strict), as at the end of every level; the cut below its
+                // core numbers is T
+                if (st->E * st->best_S > st->best_E * st->S) {
+                    st->best_E = st->E;
+                    st->best_S = st->S;
+                    st->best_pass = st->T;
+                }
+                st->T = (int32_t)jmin;
+            }
+            st->jumped = jump ? 1 : 0;
             st->nA = ta;
             st->nL = tl;
             st->edges = te;
             st->sumdeg = tdr;
             st->sumdeg_surv = tds;
+            // the least survivor degree matters only after a pass that
+            // removed nothing, which a jumped pass never is
             st->min_surv = (int32_t)min(tmin, (uint32_t)INT32_MAX);
             st->n_tiles_walk = (int32_t)((te + kWalkTile - 1) / kWalkTile);
             st->nbins = (int32_t)((tl + kBinWidth - 1) >> kBinShift);
@@ -413,6 +489,9 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
     int32_t* __restrict__ lout = live_out(w, pass);
     int32_t* __restrict__ dout = deg_out(w, pass);
     const bool filt = st->use_filt != 0;
+    // a pass the tile scan moved to the next core level: k_mark_count saw no
+    // failure, so the removal level and the live bits are written here
+    const bool jumped = st->jumped != 0;
     // a pass that leaves no survivor walks nothing: no walk tiles to mark
     const int64_t wcap = st->nL > 0 ? walk_cap : 0;
     const int64_t ntiles = (S + kMarkTile - 1) / kMarkTile;
@@ -494,6 +573,10 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
             if (prev < 0 || (prev >> 5) != (v >> 5)) w.dir[v >> 5].y = (uint32_t)pL;
             prev = v;
             if (dd[j] <= T) {
+                if (jumped) {
+                    w.removed_at[v] = T;
+                    atomicAnd(&w.dir[v >> 5].x, ~(1u << (v & 31)));
+                }
                 if (dd[j] > 0 && pA < n) {
                     w.arow[pA] = rs[j];
                     w.aoff[pA] = (int32_t)pE;
