@@ -68,7 +68,7 @@ typedef struct {
     int64_t dens_den;  /* |S~|, unreduced denominator (0 only when n = 0) */
     int32_t passes;    /* passes until the graph was empty (0 when n = 0) */
     int32_t best_pass; /* S~ is the graph left after this pass (0 = G)    */
-    int64_t best_size; /* |S~| = number of ids written to best_ids         */
+    int64_t best_size; /* |S~| = number of result ids at the front of best_ids */
 } dsg_result;
 
 /* One pass, as recorded when a trace is requested (host struct). */
@@ -140,7 +140,9 @@ size_t dsg_workspace_bytes(int64_t n, int64_t m);
  *   n, m        vertices and undirected edges; the kernels check
  *               row_ptr[0] = 0 and row_ptr[n] = 2m (DSG_EINVAL otherwise).
  *   best_ids    device, room for n int32; receives S~ in ascending order
- *               (out->best_size entries).  May be NULL to skip extraction.
+ *               (out->best_size entries; the entries after them are
+ *               overwritten with earlier candidates and hold no result).
+ *               May be NULL to skip extraction.
  *   out         host; filled on DSG_OK.
  *   workspace   device, at least dsg_workspace_bytes(n, m) bytes, 256-byte
  *               aligned; NULL makes the library allocate and free it.

@@ -50,6 +50,11 @@
 // deg(u) records in a pass, so the prefix of survivor degrees bounds every
 // bin exactly.  Rows of vertices that fail with degree 0 are not walked, and
 // nothing is walked in a pass that leaves no survivor.
+//
+// The live lists keep ascending id order (every compaction is stable and
+// pass 1 starts from 0..n-1), so the survivors of pass k, as listed for
+// pass k + 1, are S_k in the order the output wants: when pass k sets the
+// best graph, pass k + 1's k_mark_count copies its live list to best_ids.
 
 #include <hip/hip_runtime.h>
 
@@ -118,6 +123,21 @@ __device__ inline void load8(const int32_t* __restrict__ p, int64_t base, int64_
     } else {
 #pragma unroll
         for (int j = 0; j < 8; ++j) out[j] = base + j < lim ? q[j] : fill;
+    }
+}
+
+// p[base + j] = v[j] for base + j < lim; two 16-byte stores when the span is
+// whole and 16-byte aligned.
+__device__ inline void store8(int32_t* __restrict__ p, int64_t base, int64_t lim,
+                              const int32_t v[8]) {
+    int32_t* q = p + base;
+    if (base + 8 <= lim && ((uintptr_t)q & 15u) == 0) {
+        reinterpret_cast<int4*>(q)[0] = make_int4(v[0], v[1], v[2], v[3]);
+        reinterpret_cast<int4*>(q)[1] = make_int4(v[4], v[5], v[6], v[7]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (base + j < lim) q[j] = v[j];
     }
 }
 
@@ -194,9 +214,13 @@ __global__ __launch_bounds__(kBlock) void k_init(Work w, const int32_t* __restri
 
 // ------------------------------------------------------------ mark: count
 
+// `best` (may be null): S~ output.  S_k, the survivors of pass k, is this
+// pass's live list, ascending; when pass k set the best graph the list is
+// copied to `best` as it is loaded, so that after the last pass `best`
+// holds S~ (S_0 = V, best pass 0, is written by k_extract_iota instead).
 __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __restrict__ rp,
-                                                       int64_t n) {
-    const DevState* st = w.st;
+                                                       int64_t n, int32_t* __restrict__ best) {
+    DevState* st = w.st;
     if (st->done) return;
     const int32_t pass = st->pass;
     const int64_t S = st->S;
@@ -208,6 +232,8 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
     // the core number of every vertex removed at that level)
     const bool core = st->core_mode != 0;
     const int32_t rv = core ? T : pass;
+    const bool copy_best = best && !core && lin && st->best_pass == pass - 1;
+    if (copy_best && blockIdx.x == 0 && threadIdx.x == 0) st->best_count = S;
     __shared__ uint32_t red[5 * kWaves];
 
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -227,6 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
         } else {
             load8(lin, base, S, -1, vv);
             load8(din, base, S, 0, dd);
+            if (copy_best) store8(best, base, S, vv);
         }
         int32_t ll[kMarkItems];
 #pragma unroll
@@ -293,9 +320,10 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
             // their masks and one of them stores the word
             static_assert(kMarkItems == 8, "four lanes per 32-vertex word");
             if (base < S) {
+                int32_t ra[kMarkItems];
 #pragma unroll
-                for (int j = 0; j < kMarkItems; ++j)
-                    if (base + j < S) w.removed_at[base + j] = (gone8 >> j & 1u) ? rv : kNever;
+                for (int j = 0; j < kMarkItems; ++j) ra[j] = (gone8 >> j & 1u) ? rv : kNever;
+                store8(w.removed_at, base, S, ra);
             }
             uint32_t gone = gone8 << (8 * (threadIdx.x & 3));
             gone |= __shfl_xor(gone, 1, 64);
@@ -338,7 +366,18 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
 //         failures' degree sum is only totalled).
 // mode 1: the extract tiles over 0..n-1 (component x).
 
+// The records pass through LDS in chunks of up to kScanChunk tiles (132 KB),
+// so that every global load and store covers consecutive records and a pass
+// over 8192 tiles takes two round trips to memory.  Each thread sums a run
+// of consecutive tiles: one tile while the tiles fit one per thread, up to
+// kScanPer for more.  One 16-byte pad after every 32 records (a longest run)
+// keeps the runs of eight neighbouring lanes in distinct banks.
+constexpr int kScanPer = 16;
+constexpr int kScanChunk = kScanBlock * kScanPer;
+__device__ inline int scan_slot(int r) { return r + (r >> 5); }
+
 __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode, int64_t n) {
+    static_assert(kScanBlock == kBlock, "the block reductions assume kWaves waves");
     DevState* st = w.st;
     if (mode == 0) {
         if (st->done) return;
@@ -347,11 +386,9 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode,
     }
     const int64_t items = mode == 0 ? st->S : n;
     const int64_t nt = (items + kMarkTile - 1) / kMarkTile;
-    const int64_t per = (nt + kScanBlock - 1) / kScanBlock;
-    const int64_t lo = std::min<int64_t>(nt, per * threadIdx.x);
-    const int64_t hi = std::min<int64_t>(nt, lo + per);
-    __shared__ int64_t red[kScanBlock / 64];
-    __shared__ uint32_t redm[kScanBlock / 64];
+    const int tid = threadIdx.x;
+    __shared__ int4 buf[2 * kScanChunk + 2 * kScanChunk / 32];
+    __shared__ uint32_t red[5 * kWaves];
 
     // Core levels: when nothing fails at level T, the level has ended.  The
     // next level is the least degree left, and the vertices failing there
@@ -360,82 +397,102 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode,
     bool jump = false;
     uint32_t jmin = 0xFFFFFFFFu;
     if (mode == 0 && st->core_mode) {
-        int64_t l0 = 0;
+        uint32_t l0[1] = {0u};  // survivors (< 2^31)
         uint32_t mn0 = 0xFFFFFFFFu;
-        for (int64_t i = lo; i < hi; ++i) {
-            l0 += w.tiles[2 * i].y;
+        for (int64_t i = tid; i < nt; i += kScanBlock) {
+            l0[0] += (uint32_t)w.tiles[2 * i].y;
             mn0 = min(mn0, (uint32_t)w.tiles[2 * i + 1].y);
         }
-        const int64_t tl0 = block_sum<int64_t, kScanBlock / 64>(l0, red);
-        jmin = block_min<kScanBlock / 64>(mn0, redm);
-        jump = items > 0 && tl0 == items;
+        block_sum_k<1>(l0, red);
+        jmin = block_min(mn0, red);
+        jump = items > 0 && (int64_t)l0[0] == items;
     }
-    int64_t a = 0, l = 0, e = 0, dr = 0, ds = 0;
+    // running totals of the chunks before; every partial sum below is a
+    // count of vertices or of adjacency entries, so it fits 32 bits
+    int64_t ca = 0, cl = 0, ce = 0, cds = 0, cdr = 0;
     uint32_t mn = 0xFFFFFFFFu;
-    if (!jump) {
+    const int per = (int)std::min<int64_t>(
+        kScanPer, std::max<int64_t>(1, (nt + kScanBlock - 1) / kScanBlock));
+    const int chunk = per * kScanBlock;
+    for (int64_t c0 = 0; c0 < nt; c0 += chunk) {
+        const int cn = (int)std::min<int64_t>(chunk, nt - c0);
+        const int4* __restrict__ src = w.tiles + 2 * c0;
 #pragma unroll 8
-        for (int64_t i = lo; i < hi; ++i) {
-            const int4 c = w.tiles[2 * i];
-            a += c.x;
-            l += c.y;
-            e += (uint32_t)c.z;
-            dr += (uint32_t)c.w;
-            if (mode == 0) {
-                const int4 q = w.tiles[2 * i + 1];
-                ds += (uint32_t)q.x;
-                mn = min(mn, (uint32_t)q.y);
+        for (int r = tid; r < 2 * cn; r += kScanBlock) buf[scan_slot(r)] = src[r];
+        __syncthreads();
+        // this thread's run: failures with degree > 0, survivors, walk
+        // entries, survivor degrees and failure degrees
+        uint32_t v[5] = {0u, 0u, 0u, 0u, 0u};
+        const int i0 = tid * per;
+#pragma unroll 4
+        for (int k = 0; k < per; ++k) {
+            const int i = i0 + k;
+            if (i < cn) {
+                const int4 c = buf[scan_slot(2 * i)];
+                const int4 q = buf[scan_slot(2 * i + 1)];
+                if (!jump) {
+                    v[0] += (uint32_t)c.x;
+                    v[1] += (uint32_t)c.y;
+                    v[2] += (uint32_t)c.z;
+                    v[4] += (uint32_t)c.w;
+                    if (mode == 0) {
+                        v[3] += (uint32_t)q.x;
+                        mn = min(mn, (uint32_t)q.y);
+                    }
+                } else {
+                    // the next level's failures: the least-degree vertices of
+                    // the tiles whose least degree is the global one
+                    const uint32_t kk = (uint32_t)q.y == jmin ? (uint32_t)q.z : 0u;
+                    v[0] += kk;
+                    v[1] += (uint32_t)c.y - kk;
+                    v[2] += kk ? (uint32_t)q.w : 0u;
+                    v[4] += kk * jmin;
+                    v[3] += (uint32_t)q.x - kk * jmin;
+                }
             }
         }
-    } else {
-        // the next level's failures: the least-degree vertices of the tiles
-        // whose least degree is the global one
-        for (int64_t i = lo; i < hi; ++i) {
-            const int4 c = w.tiles[2 * i];
-            const int4 q = w.tiles[2 * i + 1];
-            const int64_t k = (uint32_t)q.y == jmin ? q.z : 0;
-            a += k;
-            l += c.y - k;
-            e += k ? (uint32_t)q.w : 0u;
-            dr += k * (int64_t)jmin;
-            ds += (uint32_t)q.x - k * (int64_t)jmin;
+        uint32_t tot[5];
+        block_excl_sum_k<5>(v, red, tot);
+        int64_t pa = ca + v[0], pl = cl + v[1], pe = ce + v[2], pds = cds + v[3];
+#pragma unroll 4
+        for (int k = 0; k < per; ++k) {
+            const int i = i0 + k;
+            if (i < cn) {
+                const int4 c = buf[scan_slot(2 * i)];
+                const int4 q = buf[scan_slot(2 * i + 1)];
+                buf[scan_slot(2 * i)] = make_int4((int)pa, (int)pl, (int)pe, c.w);
+                buf[scan_slot(2 * i + 1)] = make_int4((int)pds, 0, 0, 0);
+                if (!jump) {
+                    pa += (uint32_t)c.x;
+                    pl += (uint32_t)c.y;
+                    pe += (uint32_t)c.z;
+                    if (mode == 0) pds += (uint32_t)q.x;
+                } else {
+                    const int64_t kk = (uint32_t)q.y == jmin ? q.z : 0;
+                    pa += kk;
+                    pl += c.y - kk;
+                    pe += kk ? (uint32_t)q.w : 0u;
+                    pds += (uint32_t)q.x - kk * (int64_t)jmin;
+                }
+            }
         }
+        __syncthreads();
+        int4* __restrict__ dst = w.tiles + 2 * c0;
+#pragma unroll 8
+        for (int r = tid; r < 2 * cn; r += kScanBlock) dst[r] = buf[scan_slot(r)];
+        __syncthreads();  // the next chunk reuses buf
+        ca += tot[0];
+        cl += tot[1];
+        ce += tot[2];
+        cds += tot[3];
+        cdr += tot[4];
     }
-    const uint32_t tmin = block_min<kScanBlock / 64>(mn, redm);
-    int64_t ta, tl, te, tds;
-    int64_t pa = block_excl_sum<int64_t, kScanBlock / 64>(a, red, &ta);
-    int64_t pl = block_excl_sum<int64_t, kScanBlock / 64>(l, red, &tl);
-    int64_t pe = block_excl_sum<int64_t, kScanBlock / 64>(e, red, &te);
-    int64_t pds = block_excl_sum<int64_t, kScanBlock / 64>(ds, red, &tds);
-    const int64_t tdr = block_sum<int64_t, kScanBlock / 64>(dr, red);
+    const uint32_t tmin = block_min(mn, red);
+    const int64_t ta = ca, tl = cl, te = ce, tds = cds, tdr = cdr;
     // few survivors: k_mark_scatter sets their bits in a cleared filter
     const bool filt = mode == 0 && tl > 0 && tl <= kFiltBits;
     if (filt)
         for (int i = threadIdx.x; i < kFiltWords; i += kScanBlock) w.filt[i] = 0u;
-    if (!jump) {
-#pragma unroll 8
-        for (int64_t i = lo; i < hi; ++i) {
-            const int4 c = w.tiles[2 * i];
-            const int32_t cds = mode == 0 ? w.tiles[2 * i + 1].x : 0;
-            w.tiles[2 * i] = make_int4((int)pa, (int)pl, (int)pe, c.w);
-            w.tiles[2 * i + 1] = make_int4((int)pds, 0, 0, 0);
-            pa += c.x;
-            pl += c.y;
-            pe += (uint32_t)c.z;
-            pds += (uint32_t)cds;
-        }
-    } else {
-        for (int64_t i = lo; i < hi; ++i) {
-            const int4 c = w.tiles[2 * i];
-            const int4 q = w.tiles[2 * i + 1];
-            const int64_t k = (uint32_t)q.y == jmin ? q.z : 0;
-            w.tiles[2 * i] = make_int4((int)pa, (int)pl, (int)pe, c.w);
-            w.tiles[2 * i + 1] = make_int4((int)pds, 0, 0, 0);
-            pa += k;
-            pl += c.y - k;
-            pe += k ? (uint32_t)q.w : 0u;
-            pds += (uint32_t)q.x - k * (int64_t)jmin;
-        }
-    }
     if (threadIdx.x == 0) {
         if (mode == 0) {
             if (jump) {
@@ -496,6 +553,9 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
     const int64_t wcap = st->nL > 0 ? walk_cap : 0;
     const int64_t ntiles = (S + kMarkTile - 1) / kMarkTile;
     __shared__ uint32_t red[3 * kWaves];
+    // the tile's walk-list rows (row start, prefix), staged so that they are
+    // stored as consecutive runs
+    __shared__ int32_t s_row[kMarkTile], s_off[kMarkTile];
 
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t base = t * kMarkTile + (int64_t)threadIdx.x * kMarkItems;
@@ -562,7 +622,9 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
         uint32_t ex[3] = {cA | (cL << 16), cE, cDs}, tot[3];
         block_excl_sum_k<3>(ex, red, tot);
         const uint32_t ex_packed = ex[0], ex_e = ex[1], ex_ds = ex[2];
-        int64_t pA = (int64_t)tp.x + (ex_packed & 0xFFFFu);
+        const int64_t a0 = tp.x;  // the tile's first walk-list slot
+        const int32_t tot_a = (int32_t)(tot[0] & 0xFFFFu);
+        int64_t pA = a0 + (ex_packed & 0xFFFFu);
         int64_t pL = (int64_t)tp.y + (ex_packed >> 16);
         int64_t pE = (int64_t)(uint32_t)tp.z + ex_e;
         int64_t pD = (int64_t)(uint32_t)tq.x + ex_ds;
@@ -578,8 +640,8 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
                     atomicAnd(&w.dir[v >> 5].x, ~(1u << (v & 31)));
                 }
                 if (dd[j] > 0 && pA < n) {
-                    w.arow[pA] = rs[j];
-                    w.aoff[pA] = (int32_t)pE;
+                    s_row[pA - a0] = rs[j];
+                    s_off[pA - a0] = (int32_t)pE;
                     const int64_t len = ll[j];
                     // walk tiles whose first entry lies in [pE, pE + len)
                     for (int64_t tt = (pE + kWalkTile - 1) / kWalkTile;
@@ -602,6 +664,12 @@ __global__ __launch_bounds__(kBlock) void k_mark_scatter(Work w, const int32_t* 
                 ++pL;
                 pD += dd[j];
             }
+        }
+        // (the next tile writes s_row only after the barriers of its scan)
+        __syncthreads();
+        for (int i = threadIdx.x; i < tot_a && a0 + i < n; i += kBlock) {
+            w.arow[a0 + i] = s_row[i];
+            w.aoff[a0 + i] = s_off[i];
         }
     }
 }
@@ -1230,6 +1298,18 @@ __global__ __launch_bounds__(kBlock) void k_extract_scatter(Work w, int64_t n,
     }
 }
 
+// S~ when the best graph is the whole graph (best pass 0): 0..n-1.  Any
+// other S~ is a pass's survivor list, which k_mark_count has copied.
+__global__ __launch_bounds__(kBlock) void k_extract_iota(Work w, int64_t n,
+                                                         int32_t* __restrict__ best) {
+    DevState* st = w.st;
+    if (!st->done || st->status != kStOk || st->best_pass != 0) return;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += stride)
+        best[v] = (int32_t)v;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->best_count = n;
+}
+
 // ================================================================ CBDS-P
 // Phase 2 of Algorithm 2 (Section 3.2), after the k-core levels.  removed_at
 // holds every vertex's core number; the densest core is C_K = { v : core(v)
@@ -1593,7 +1673,8 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
     for (;;) {
         for (int32_t b = 0; b < batch; ++b) {
             DSG_HIP(log.begin(kKindMark));
-            k_mark_count<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, n);
+            k_mark_count<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, n,
+                                                      core_mode ? nullptr : best_ids);
             k_scan_tiles<<<1, kScanBlock, 0, s>>>(w, 0, n);
             k_mark_scatter<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, n, walk_tiles(m),
                                                         nbins_cap);
@@ -1612,10 +1693,9 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
             ++launched;
         }
         if (best_ids && !core_mode) {
+            // S~ is already in best_ids unless it is the whole graph
             DSG_HIP(log.begin(kKindExtract));
-            k_extract_count<<<mark_grid, kBlock, 0, s>>>(w, n, nullptr);
-            k_scan_tiles<<<1, kScanBlock, 0, s>>>(w, 1, n);
-            k_extract_scatter<<<mark_grid, kBlock, 0, s>>>(w, n, best_ids, nullptr);
+            k_extract_iota<<<init_grid, kBlock, 0, s>>>(w, n, best_ids);
             DSG_HIP(hipGetLastError());
             DSG_HIP(log.end());
         }

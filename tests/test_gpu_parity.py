@@ -183,6 +183,29 @@ def test_without_extraction(dsg):
     assert (r.passes, r.best_pass, r.num, r.den) == (o.passes, o.best_pass, o.num, o.den)
 
 
+def test_best_ids_in_a_caller_buffer(dsg):
+    # S~ reaches best_ids as the survivor list of the best pass (copied by
+    # the pass after it) or, when the whole graph stays the best, as 0..n-1;
+    # the cases cover best pass 0, the last non-empty pass, a middle pass,
+    # and a later best replacing a larger earlier one in the same buffer
+    import torch
+    cases = [(inputs.cycle(1_000_003), (1, 10)),
+             (inputs.disjoint_cliques(50, 10), (1, 10)),
+             (inputs.rmat(16, 16, seed=5), (1, 10)),
+             (inputs.rmat(17, 16, seed=6), (0, 1))]
+    seen = set()
+    for g, e in cases:
+        o = oracle.peel_graph(g, *e, trace=False)
+        seen.add("zero" if o.best_pass == 0 else "last" if o.best_pass == o.passes - 1 else "mid")
+        rp, ci = to_device(g)
+        buf = torch.full((g.n + 5,), -7, dtype=torch.int32, device="cuda")
+        r = dsg.peel(rp, ci, e, best_ids=buf)
+        assert (r.passes, r.best_pass, r.num, r.den) == (o.passes, o.best_pass, o.num, o.den), g.name
+        assert np.array_equal(buf[:o.best.size].cpu().numpy(), o.best), g.name
+        assert bool((buf[g.n:] == -7).all()), g.name
+    assert seen == {"zero", "last", "mid"}
+
+
 def test_repeated_runs_identical(dsg):
     g = inputs.rmat(16, 16, seed=41)
     rp, ci = to_device(g)
