@@ -142,8 +142,9 @@ __device__ inline void store8(int32_t* __restrict__ p, int64_t base, int64_t lim
 }
 
 // ------------------------------------------------------------------ init
-// Two kernels so that the per-vertex kernel can flag a bad row_ptr without
-// racing the initialisation of the state.
+// The state only: pass 1 reads every row offset (and flags a row_ptr that
+// decreases anywhere before any later kernel uses one as an address) and
+// writes every removal pass and every live-bit word.
 
 __global__ void k_init_state(Work w, const int32_t* __restrict__ rp, int64_t n, int64_t m,
                              int64_t num, int64_t den, int32_t max_pass, int32_t trace_cap,
@@ -193,25 +194,6 @@ __global__ void k_init_state(Work w, const int32_t* __restrict__ rp, int64_t n, 
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_init(Work w, const int32_t* __restrict__ rp,
-                                                 int64_t n) {
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    bool bad = false;
-    // removed_at needs no initialisation: pass 1 writes every entry
-    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += stride)
-        bad |= rp[v + 1] < rp[v];
-    const int64_t nw = (n + 31) >> 5;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nw; i += stride) {
-        const int64_t left = n - i * 32;
-        w.dir[i] = make_uint2(left >= 32 ? 0xFFFFFFFFu : ((1u << left) - 1u), 0u);
-    }
-    if (bad) {
-        // every writer stores the same values; later kernels see them
-        w.st->status = kStBadRowPtr;
-        w.st->done = 1;
-    }
-}
-
 // ------------------------------------------------------------ mark: count
 
 // `best` (may be null): S~ output.  S_k, the survivors of pass k, is this
@@ -249,6 +231,15 @@ __global__ __launch_bounds__(kBlock) void k_mark_count(Work w, const int32_t* __
             for (int j = 0; j < kMarkItems; ++j) {
                 vv[j] = base + j < S ? (int32_t)(base + j) : -1;
                 dd[j] = (j + 1 < kMarkItems ? r[j + 1] : r8) - r[j];
+            }
+            // a row_ptr that decreases is no CSR: every later kernel sees
+            // the run done (every writer stores the same values)
+            bool bad = false;
+#pragma unroll
+            for (int j = 0; j < kMarkItems; ++j) bad |= vv[j] >= 0 && dd[j] < 0;
+            if (bad) {
+                st->status = kStBadRowPtr;
+                st->done = 1;
             }
         } else {
             load8(lin, base, S, -1, vv);
@@ -1666,7 +1657,6 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
                                   (int32_t)items_cap,
                                   launch && (launch->flags & DSG_LAUNCH_BIN_REGIONS) ? 1 : 0,
                                   core_mode);
-    k_init<<<init_grid, kBlock, 0, s>>>(w, g->row_ptr, n);
     DSG_HIP(hipGetLastError());
     DSG_HIP(log.end());
 
