@@ -203,6 +203,15 @@ def test_best_ids_in_a_caller_buffer(dsg):
         assert (r.passes, r.best_pass, r.num, r.den) == (o.passes, o.best_pass, o.num, o.den), g.name
         assert np.array_equal(buf[:o.best.size].cpu().numpy(), o.best), g.name
         assert bool((buf[g.n:] == -7).all()), g.name
+        # outputs 4 and 12 bytes past a 16-byte boundary: the copies and
+        # the pass-1 removal writes take their element-wise path
+        buf2 = torch.full((g.n + 8,), -7, dtype=torch.int32, device="cuda")
+        rem2 = torch.full((g.n + 8,), -7, dtype=torch.int32, device="cuda")
+        r = dsg.peel(rp, ci, e, best_ids=buf2[1:], removed_at=rem2[3:])
+        assert (r.passes, r.best_pass, r.num, r.den) == (o.passes, o.best_pass, o.num, o.den), g.name
+        assert np.array_equal(buf2[1:1 + o.best.size].cpu().numpy(), o.best), g.name
+        assert np.array_equal(rem2[3:3 + g.n].cpu().numpy(), o.removed_at), g.name
+        assert int(buf2[0]) == -7 and bool((rem2[:3] == -7).all()) and bool((rem2[3 + g.n:] == -7).all())
     assert seen == {"zero", "last", "mid"}
 
 
