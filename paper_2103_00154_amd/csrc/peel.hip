@@ -59,6 +59,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -93,6 +94,7 @@ struct Work {
     uint32_t* filt;       // kFiltWords: survivor filter of the current pass
     unsigned long long* wpart;  // kMaxWalkGrid: decrement records per walk workgroup
     PassRecord* trace;    // kTraceCap
+    int64_t* progress;    // pinned host word the tile scan posts to, or null
 };
 
 static_assert(sizeof(PassRecord) == sizeof(dsg_pass_trace), "trace layout");
@@ -367,11 +369,23 @@ constexpr int kScanPer = 16;
 constexpr int kScanChunk = kScanBlock * kScanPer;
 __device__ inline int scan_slot(int r) { return r + (r >> 5); }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode, int64_t n) {
+// Posts 2 * seq + final to the host's progress word (system scope, so that
+// the host sees it while the pass is still running): `seq` numbers the
+// passes the host has enqueued, `final` says that no pass after this one
+// has work, so the host enqueues no more.
+__device__ inline void post_progress(int64_t* p, int64_t seq, bool fin) {
+    __hip_atomic_store(p, 2 * seq + (fin ? 1 : 0), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode, int64_t n,
+                                                           int64_t seq) {
     static_assert(kScanBlock == kBlock, "the block reductions assume kWaves waves");
     DevState* st = w.st;
     if (mode == 0) {
-        if (st->done) return;
+        if (st->done) {
+            if (threadIdx.x == 0 && w.progress) post_progress(w.progress, seq, true);
+            return;
+        }
     } else {
         if (!st->done || st->status != kStOk) return;
     }
@@ -516,6 +530,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode,
             st->cross = 0;
             w.aoff[ta] = (int32_t)te;
             w.bin_start[st->nbins] = (int32_t)tds;
+            // a pass that leaves no survivor ends the run
+            if (w.progress) post_progress(w.progress, seq, tl == 0);
         } else {
             st->best_count = ta;
         }
@@ -1490,6 +1506,31 @@ Layout layout(int64_t n, int64_t m) {
 
 
 thread_local DevState* t_host_state = nullptr;
+// the tile scan's progress word (pinned, coherent host memory)
+thread_local int64_t* t_progress = nullptr;
+
+// Waits until the progress word reaches `want` and returns it; returns -1
+// once the stream has no work left or has failed without that, so that the
+// wait always ends.  The stream is queried only after 20 ms without the
+// post: a query adds a marker to the stream, which costs every pass a gap.
+static int64_t wait_progress(const int64_t* p, int64_t want, hipStream_t s) {
+    auto last = std::chrono::steady_clock::now();
+    for (uint32_t spin = 1;; ++spin) {
+        const int64_t v = __atomic_load_n(p, __ATOMIC_ACQUIRE);
+        if (v >= want) return v;
+        if ((spin & 1023) == 0) {
+            const auto now = std::chrono::steady_clock::now();
+            if (now - last > std::chrono::milliseconds(20)) {
+                last = now;
+                if (hipStreamQuery(s) != hipErrorNotReady) {
+                    const int64_t u = __atomic_load_n(p, __ATOMIC_ACQUIRE);
+                    return u >= want ? u : -1;
+                }
+            }
+        }
+        __builtin_ia32_pause();
+    }
+}
 
 enum { kKindInit = 0, kKindMark = 1, kKindWalk = 2, kKindApply = 3, kKindExtract = 4 };
 
@@ -1604,6 +1645,11 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
         DSG_HIP(hipHostMalloc(&p, sizeof(DevState), hipHostMallocDefault));
         t_host_state = (DevState*)p;
     }
+    if (!t_progress) {
+        void* p = nullptr;
+        DSG_HIP(hipHostMalloc(&p, 64, hipHostMallocCoherent));
+        t_progress = (int64_t*)p;
+    }
     if (!base) {
         DSG_HIP(hipMalloc((void**)&base, L.total));
         owned = true;
@@ -1629,6 +1675,7 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
     w.filt = (uint32_t*)(base + L.filt);
     w.wpart = (unsigned long long*)(base + L.wpart);
     w.trace = (PassRecord*)(base + L.trace);
+    w.progress = nullptr;
 
     // core levels: every pass removes a vertex or ends a level, and every
     // level after the first removes a vertex, so 2n + 1 passes suffice
@@ -1660,26 +1707,53 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
     DSG_HIP(hipGetLastError());
     DSG_HIP(log.end());
 
-    for (;;) {
-        for (int32_t b = 0; b < batch; ++b) {
-            DSG_HIP(log.begin(kKindMark));
+    {
+        // One pass, seven launches; `seq` numbers it for the progress word.
+        auto pass_launches = [&](int64_t seq) -> hipError_t {
+            hipError_t e = log.begin(kKindMark);
+            if (e != hipSuccess) return e;
             k_mark_count<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, n,
                                                       core_mode ? nullptr : best_ids);
-            k_scan_tiles<<<1, kScanBlock, 0, s>>>(w, 0, n);
+            k_scan_tiles<<<1, kScanBlock, 0, s>>>(w, 0, n, seq);
             k_mark_scatter<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, n, walk_tiles(m),
                                                         nbins_cap);
-            DSG_HIP(hipGetLastError());
-            DSG_HIP(log.end());
-            DSG_HIP(log.begin(kKindWalk));
+            if ((e = hipGetLastError()) != hipSuccess || (e = log.end()) != hipSuccess ||
+                (e = log.begin(kKindWalk)) != hipSuccess)
+                return e;
             k_walk<<<walk_grid, kBlock, 0, s>>>(w, g->col_idx, (uint32_t)n, (uint32_t)(2 * m));
-            DSG_HIP(hipGetLastError());
-            DSG_HIP(log.end());
-            DSG_HIP(log.begin(kKindApply));
+            if ((e = hipGetLastError()) != hipSuccess || (e = log.end()) != hipSuccess ||
+                (e = log.begin(kKindApply)) != hipSuccess)
+                return e;
             k_walk_finish<<<1, kBlock, 0, s>>>(w, (int32_t)walk_grid);
             k_apply<<<apply_grid, kApplyBlock, 0, s>>>(w);
             k_reduce<<<reduce_grid, kBlock, 0, s>>>(w);
-            DSG_HIP(hipGetLastError());
-            DSG_HIP(log.end());
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            return log.end();
+        };
+
+    // Peeling passes run one pass ahead of the host: pass k's tile scan
+    // posts whether pass k leaves survivors, and the host enqueues pass k + 1
+    // on that, while pass k's walk and degree updates still run.  No pass is
+    // then enqueued after the last one.  Core levels (many light passes,
+    // grids resized between batches) and an explicit pass batch use batches
+    // of passes with a host check after each; so does the rest of a peel
+    // whose post did not come (the stream drained or failed first).
+    const bool ahead = !core_mode && !(launch && launch->pass_batch);
+    if (ahead) {
+        __atomic_store_n(t_progress, (int64_t)0, __ATOMIC_RELEASE);
+        w.progress = t_progress;
+        for (int64_t seq = 1;; ++seq) {
+            DSG_HIP(pass_launches(seq));
+            ++launched;
+            const int64_t v = wait_progress(t_progress, 2 * seq, s);
+            if (v < 0 || (v & 1) || launched > (int64_t)max_pass) break;
+        }
+        w.progress = nullptr;
+    }
+
+    for (bool first = true;; first = false) {
+        for (int32_t b = 0; b < batch && !(first && ahead); ++b) {
+            DSG_HIP(pass_launches(0));
             ++launched;
         }
         if (best_ids && !core_mode) {
@@ -1712,6 +1786,7 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
             reduce_grid = (unsigned)std::max<int64_t>(1, std::min(cap, (S * 16 + kBlock - 1) / kBlock));
         }
     }
+    }  // pass_launches
     if (core_mode && t_host_state->status == kStOk) {
         // CBDS-P phase 2, then S = C_K plus the legitimate vertices; the
         // live lists and a degree array are free now and hold the flags and
@@ -1726,7 +1801,7 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
         k_cbds_pairs<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, g->col_idx, n, flag, llist);
         if (best_ids) {
             k_extract_count<<<mark_grid, kBlock, 0, s>>>(w, n, flag);
-            k_scan_tiles<<<1, kScanBlock, 0, s>>>(w, 1, n);
+            k_scan_tiles<<<1, kScanBlock, 0, s>>>(w, 1, n, 0);
             k_extract_scatter<<<mark_grid, kBlock, 0, s>>>(w, n, best_ids, flag);
         }
         DSG_HIP(hipGetLastError());
