@@ -89,7 +89,12 @@ typedef struct {
 typedef struct {
     int32_t mark_grid;  /* workgroups of the mark / extract kernels */
     int32_t walk_grid;  /* workgroups of the neighbour-walk kernel (at most 4096 are used) */
-    int32_t pass_batch; /* passes enqueued before the host checks for completion */
+    int32_t pass_batch; /* 0: a peel runs one pass ahead of the device (each
+                         * pass's tile scan posts to a pinned host word whether
+                         * the pass leaves survivors, and the host then
+                         * enqueues the next pass); > 0: passes are enqueued in
+                         * batches of this many (doubling up to 64) with a host
+                         * check after each.  CBDS-P always uses batches. */
     int32_t flags;      /* DSG_LAUNCH_* bits */
 } dsg_launch;
 

@@ -260,9 +260,13 @@ class Server:
                     dev = ints[o_csr // 4:o_csr // 4 + g.csr.numel()]
                     dev.copy_(g.csr, non_blocking=True)
                     best = ints[o_best // 4:o_best // 4 + max(g.n, 1)]
+                    # passes in batches of eight with one host check each:
+                    # next to the batch launches of other threads, waiting
+                    # on the device before every pass (the default) exposes
+                    # each pass's launches to the contended runtime
                     r = dsg.peel(dev[:g.n + 1], dev[g.n + 1:] if g.m else dev[:1], rq.eps,
                                  m=g.m, best_ids=best, workspace=self.buf[o_ws:o_ws + nb_ws],
-                                 stream=stream)
+                                 launch={"pass_batch": 8}, stream=stream)
                     b = r.best.cpu().numpy()
                 rq.result = {"num": r.num, "den": r.den, "passes": r.passes,
                              "best_pass": r.best_pass, "best_size": len(b), "status": 0}
