@@ -103,6 +103,11 @@ typedef struct {
  * a pass leaves more than 1024 * 32768 survivors; the flag forces it. */
 #define DSG_LAUNCH_BIN_REGIONS 1
 
+/* The tile scan posts no progress, so a peel running one pass ahead of the
+ * device waits for a post that does not come: after 20 ms with the stream
+ * idle it finishes with batches of passes.  For testing that path. */
+#define DSG_LAUNCH_NO_PROGRESS 2
+
 /* Optional per-kernel timing, measured with HIP events on the call's stream
  * around every launch of the call (host struct, filled on return).  Launches
  * enqueued after the last pass return at once and are counted too. */

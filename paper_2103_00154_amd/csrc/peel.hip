@@ -1741,7 +1741,7 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
     const bool ahead = !core_mode && !(launch && launch->pass_batch);
     if (ahead) {
         __atomic_store_n(t_progress, (int64_t)0, __ATOMIC_RELEASE);
-        w.progress = t_progress;
+        w.progress = launch && (launch->flags & DSG_LAUNCH_NO_PROGRESS) ? nullptr : t_progress;
         for (int64_t seq = 1;; ++seq) {
             DSG_HIP(pass_launches(seq));
             ++launched;

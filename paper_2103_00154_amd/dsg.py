@@ -52,6 +52,7 @@ class Launch(ctypes.Structure):
 
 #: dsg_launch.flags bit: keep degree-update records in per-bin regions
 LAUNCH_BIN_REGIONS = 1
+LAUNCH_NO_PROGRESS = 2
 
 
 class Profile(ctypes.Structure):
@@ -236,7 +237,8 @@ def peel(row_ptr, col_idx, eps=(1, 10), *, m: int | None = None, extract: bool =
     if launch:
         ln = Launch(int(launch.get("mark_grid", 0)), int(launch.get("walk_grid", 0)),
                     int(launch.get("pass_batch", 0)),
-                    LAUNCH_BIN_REGIONS if launch.get("bin_regions") else 0)
+                    (LAUNCH_BIN_REGIONS if launch.get("bin_regions") else 0)
+                    | (LAUNCH_NO_PROGRESS if launch.get("no_progress") else 0))
     prof = Profile() if profile else None
     res = Result()
     with torch.cuda.device(dev):

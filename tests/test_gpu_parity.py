@@ -117,6 +117,9 @@ def _rmat20():
     {"walk_grid": 1}, {"walk_grid": 3, "mark_grid": 1}, {"walk_grid": 64, "mark_grid": 7},
     {"pass_batch": 1}, {"pass_batch": 2, "walk_grid": 1000}, {"mark_grid": 5000},
     {"bin_regions": True}, {"bin_regions": True, "walk_grid": 5, "pass_batch": 1},
+    # no progress posts: the peel waits out the 20 ms limit once, then
+    # finishes with batches of passes
+    {"no_progress": True}, {"no_progress": True, "walk_grid": 7},
 ])
 def test_launch_shape_does_not_change_results(dsg, launch):
     g = inputs.chung_lu(200_000, 24, 2.2, 12)
