@@ -218,6 +218,41 @@ def test_best_ids_in_a_caller_buffer(dsg):
     assert seen == {"zero", "last", "mid"}
 
 
+def test_concurrent_peels_from_two_threads(dsg):
+    # each calling thread has its own progress word for the passes it runs
+    # ahead; two threads peel different graphs on their own streams at once
+    import threading
+    import torch
+    graphs = [(inputs.rmat(16, 16, seed=61), (1, 10)), (inputs.chung_lu(60_000, 20, 2.3, 62), (0, 1))]
+    want = [oracle.peel_graph(g, *e) for g, e in graphs]
+    dev = [to_device(g) for g, _ in graphs]
+    torch.cuda.synchronize()
+    got = [[], []]
+    errors = []
+
+    def run(i):
+        try:
+            s = torch.cuda.Stream()
+            for _ in range(6):
+                with torch.cuda.stream(s):
+                    r = dsg.peel(*dev[i], graphs[i][1], removed_at=True, trace=True, stream=s)
+                s.synchronize()
+                got[i].append(r)
+        except BaseException as exc:  # reported by the main thread
+            errors.append(exc)
+
+    threads = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not errors, errors
+    for i, (g, _) in enumerate(graphs):
+        assert len(got[i]) == 6
+        for r in got[i]:
+            assert_same(r, want[i], g.n)
+
+
 def test_repeated_runs_identical(dsg):
     g = inputs.rmat(16, 16, seed=41)
     rp, ci = to_device(g)
