@@ -1707,29 +1707,29 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
     DSG_HIP(hipGetLastError());
     DSG_HIP(log.end());
 
-    {
-        // One pass, seven launches; `seq` numbers it for the progress word.
-        auto pass_launches = [&](int64_t seq) -> hipError_t {
-            hipError_t e = log.begin(kKindMark);
-            if (e != hipSuccess) return e;
-            k_mark_count<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, n,
-                                                      core_mode ? nullptr : best_ids);
-            k_scan_tiles<<<1, kScanBlock, 0, s>>>(w, 0, n, seq);
-            k_mark_scatter<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, n, walk_tiles(m),
-                                                        nbins_cap);
-            if ((e = hipGetLastError()) != hipSuccess || (e = log.end()) != hipSuccess ||
-                (e = log.begin(kKindWalk)) != hipSuccess)
-                return e;
-            k_walk<<<walk_grid, kBlock, 0, s>>>(w, g->col_idx, (uint32_t)n, (uint32_t)(2 * m));
-            if ((e = hipGetLastError()) != hipSuccess || (e = log.end()) != hipSuccess ||
-                (e = log.begin(kKindApply)) != hipSuccess)
-                return e;
-            k_walk_finish<<<1, kBlock, 0, s>>>(w, (int32_t)walk_grid);
-            k_apply<<<apply_grid, kApplyBlock, 0, s>>>(w);
-            k_reduce<<<reduce_grid, kBlock, 0, s>>>(w);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            return log.end();
-        };
+    {  // the scope of pass_launches, which the error paths jump past
+    // One pass, seven launches; `seq` numbers it for the progress word.
+    auto pass_launches = [&](int64_t seq) -> hipError_t {
+        hipError_t e = log.begin(kKindMark);
+        if (e != hipSuccess) return e;
+        k_mark_count<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, n,
+                                                  core_mode ? nullptr : best_ids);
+        k_scan_tiles<<<1, kScanBlock, 0, s>>>(w, 0, n, seq);
+        k_mark_scatter<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, n, walk_tiles(m),
+                                                    nbins_cap);
+        if ((e = hipGetLastError()) != hipSuccess || (e = log.end()) != hipSuccess ||
+            (e = log.begin(kKindWalk)) != hipSuccess)
+            return e;
+        k_walk<<<walk_grid, kBlock, 0, s>>>(w, g->col_idx, (uint32_t)n, (uint32_t)(2 * m));
+        if ((e = hipGetLastError()) != hipSuccess || (e = log.end()) != hipSuccess ||
+            (e = log.begin(kKindApply)) != hipSuccess)
+            return e;
+        k_walk_finish<<<1, kBlock, 0, s>>>(w, (int32_t)walk_grid);
+        k_apply<<<apply_grid, kApplyBlock, 0, s>>>(w);
+        k_reduce<<<reduce_grid, kBlock, 0, s>>>(w);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        return log.end();
+    };
 
     // Peeling passes run one pass ahead of the host: pass k's tile scan
     // posts whether pass k leaves survivors, and the host enqueues pass k + 1
