@@ -1135,6 +1135,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply(Work w) {
     const int32_t mode = st->walk_mode;
     const int64_t tstride = st->toff_stride;
     __shared__ int32_t cnt[kBinWidth];
+    __shared__ uint32_t se[kApplyTiles];  // (start | end << 16) of a tile's run
     const uint16_t* __restrict__ recs = w.recs;
     const int lanes = st->apply_lanes;
     const int groups = kApplyBlock / lanes;
@@ -1147,38 +1148,33 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply(Work w) {
         __syncthreads();
         if (mode == 0) {
             // groups of `lanes` threads walk one tile's run of this bin's
-            // records; the next tile's run bounds load while this run counts
-            int64_t tt = (int64_t)item.y + grp;
-            int32_t s = 0, e = 0;
-            if (tt < item.z) {
-                const uint16_t* __restrict__ o = w.toff + tt * tstride + item.x;
-                s = o[0];
-                e = o[1];
-            }
-            while (tt < item.z) {
-                const int64_t tn = tt + groups;
-                int32_t sn = 0, en = 0;
-                if (tn < item.z) {
-                    const uint16_t* __restrict__ o = w.toff + tn * tstride + item.x;
-                    sn = o[0];
-                    en = o[1];
+            // records; the runs' bounds of up to kApplyTiles tiles are
+            // loaded into LDS first, all at once, so that no group waits
+            // on a bounds load between two runs
+            for (int64_t c0 = item.y; c0 < item.z; c0 += kApplyTiles) {
+                const int32_t cn = (int32_t)std::min<int64_t>(kApplyTiles, item.z - c0);
+                for (int32_t i = threadIdx.x; i < cn; i += kApplyBlock) {
+                    const uint16_t* __restrict__ o = w.toff + (c0 + i) * tstride + item.x;
+                    se[i] = (uint32_t)o[0] | ((uint32_t)o[1] << 16);
                 }
-                const uint16_t* __restrict__ r = recs + tt * (int64_t)kWalkTile;
-                for (int32_t x0 = s + sub; x0 < e; x0 += kApplyBatch * lanes) {
-                    // issue the batch's loads before any count
-                    uint32_t v[kApplyBatch];
+                __syncthreads();
+                for (int32_t i = grp; i < cn; i += groups) {
+                    const int32_t s = (int32_t)(se[i] & 0xFFFFu), e = (int32_t)(se[i] >> 16);
+                    const uint16_t* __restrict__ r = recs + (c0 + i) * (int64_t)kWalkTile;
+                    for (int32_t x0 = s + sub; x0 < e; x0 += kApplyBatch * lanes) {
+                        // issue the batch's loads before any count
+                        uint32_t v[kApplyBatch];
 #pragma unroll
-                    for (int k = 0; k < kApplyBatch; ++k) {
-                        const int32_t x = x0 + k * lanes;
-                        v[k] = x < e ? (uint32_t)r[x] : 0xFFFFFFFFu;
+                        for (int k = 0; k < kApplyBatch; ++k) {
+                            const int32_t x = x0 + k * lanes;
+                            v[k] = x < e ? (uint32_t)r[x] : 0xFFFFFFFFu;
+                        }
+#pragma unroll
+                        for (int k = 0; k < kApplyBatch; ++k)
+                            if (v[k] != 0xFFFFFFFFu) atomicAdd(&cnt[v[k]], 1);
                     }
-#pragma unroll
-                    for (int k = 0; k < kApplyBatch; ++k)
-                        if (v[k] != 0xFFFFFFFFu) atomicAdd(&cnt[v[k]], 1);
                 }
-                tt = tn;
-                s = sn;
-                e = en;
+                __syncthreads();  // se is reloaded for the next tiles
             }
         } else {
             int64_t e = (int64_t)item.y + threadIdx.x;
