@@ -148,7 +148,8 @@ def main() -> int:
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} (WORLD_SIZE {world}) is not "
-              "supported by this build: the peel of one graph runs on a single MI355X.",
+              "supported: the library peels one graph on a single MI355X (how the peel would "
+              "shard over several GPUs is described in the design notes, not implemented).",
               file=sys.stderr)
         return 2
 
