@@ -29,7 +29,7 @@ constexpr int kBinWidth = 1 << kBinShift;        // 32768 ranks: 128 KB of LDS c
 constexpr int kNbLds = 1024;                     // bins the walk can stage in LDS
 constexpr int kScanBlock = 256;                  // threads of the tile-scan workgroup
 constexpr int kApplyBlock = 1024;                // threads of an apply workgroup
-constexpr int kApplyBatch = 8;                   // record loads per lane before counting
+constexpr int kApplyBatch = 16;                  // record loads per lane before counting
 constexpr int kApplyTiles = 2048;                // tiles whose run bounds k_apply stages in LDS
 constexpr int64_t kChunkMin = 8192;              // least records per apply work item
 constexpr int64_t kTargetItems = 512;            // apply work items aimed for per pass
