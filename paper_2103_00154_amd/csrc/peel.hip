@@ -1216,23 +1216,28 @@ __global__ __launch_bounds__(kBlock) void k_reduce(Work w) {
     const int rr = lane_id() % ranks_per_wave;
     for (int64_t task = blockIdx.x; task < ntasks; task += gridDim.x) {
         const int64_t r = task * per_block + (int64_t)wave_id() * ranks_per_wave + rr;
+        // every load below is unconditional, at a clamped index, and only
+        // counted when in range (a load under a condition is waited for at
+        // once): the rank's degree with its partial rows, 8 rows per lane
+        // in flight
+        const int64_t rc = std::min<int64_t>(r, nL - 1);
+        const int2 bi = w.bin_items[rc >> kBinShift];
+        const int32_t d0 = deg[rc];
         int32_t sum = 0;
-        if (r < nL) {
-            const int2 bi = w.bin_items[r >> kBinShift];
+        if (r < nL && bi.y > 0) {
             const int32_t* __restrict__ p =
                 w.partial + (int64_t)bi.x * stride + (r & (kBinWidth - 1));
-            int32_t i = sub;
-            for (; i + 3 * lanes < bi.y; i += 4 * lanes) {
-                const int32_t a = p[(int64_t)i * stride];
-                const int32_t b = p[(int64_t)(i + lanes) * stride];
-                const int32_t c = p[(int64_t)(i + 2 * lanes) * stride];
-                const int32_t d = p[(int64_t)(i + 3 * lanes) * stride];
-                sum += a + b + c + d;
+            for (int32_t i = sub; i < bi.y; i += 8 * lanes) {
+                int32_t v[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    v[k] = p[(int64_t)std::min(i + k * lanes, bi.y - 1) * stride];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) sum += i + k * lanes < bi.y ? v[k] : 0;
             }
-            for (; i < bi.y; i += lanes) sum += p[(int64_t)i * stride];
         }
         for (int off = ranks_per_wave; off < 64; off <<= 1) sum += __shfl_xor(sum, off, 64);
-        if (sub == 0 && r < nL && sum) deg[r] -= sum;
+        if (sub == 0 && r < nL && sum) deg[r] = d0 - sum;
     }
 }
 
