@@ -12,6 +12,7 @@ import random
 
 import numpy as np
 import pytest
+from hypothesis import HealthCheck, given, settings, strategies as st
 
 import oracle
 from gpu_util import assert_same, check, say, to_device
@@ -63,6 +64,28 @@ def test_sampled_small_graphs(dsg):
         rp, ci = to_device(g)
         r = dsg.peel(rp, ci, e, removed_at=True, trace=True)
         assert_same(r, oracle.peel_graph(g, *e), n)
+
+
+@st.composite
+def _hyp_graphs(draw):
+    """A graph on 1..40 vertices: each vertex pair is an edge with a drawn
+    probability, plus an eps from the tested set."""
+    n = draw(st.integers(1, 40))
+    p = draw(st.sampled_from([0.05, 0.15, 0.4, 0.8]))
+    seed = draw(st.integers(0, 2**30))
+    e = draw(st.sampled_from(EPS))
+    return n, p, seed, e
+
+
+@settings(max_examples=150, deadline=None, derandomize=True,
+          suppress_health_check=[HealthCheck.function_scoped_fixture])
+@given(case=_hyp_graphs())
+def test_hypothesis_graphs(dsg, case):
+    n, p, seed, e = case
+    g = inputs.random_small(n, p, seed)
+    rp, ci = to_device(g)
+    r = dsg.peel(rp, ci, e, removed_at=True, trace=True)
+    assert_same(r, oracle.peel_graph(g, *e), n)
 
 
 def _tile_edge_graphs():

@@ -16,6 +16,7 @@ import random
 
 import numpy as np
 import pytest
+from hypothesis import given, settings, strategies as st
 
 import oracle
 from oracle import exact, literal
@@ -93,6 +94,26 @@ def test_sampled_six_and_seven_vertex_graphs_match_literal():
             mask = rnd.getrandbits(len(pairs))
             g = inputs.from_edges(n, [p for i, p in enumerate(pairs) if mask >> i & 1])
             _same(g, rnd.choice(EPS))
+
+
+@st.composite
+def _hyp_graphs(draw, max_n=12):
+    """A graph on 1..max_n vertices with any edge set (each possible edge
+    drawn independently), plus an eps from the tested set."""
+    n = draw(st.integers(1, max_n))
+    pairs = list(itertools.combinations(range(n), 2))
+    keep = draw(st.lists(st.booleans(), min_size=len(pairs), max_size=len(pairs)))
+    e = draw(st.sampled_from(EPS))
+    return n, [p for p, k in zip(pairs, keep) if k], e
+
+
+@settings(max_examples=400, deadline=None, derandomize=True)
+@given(_hyp_graphs())
+def test_hypothesis_graphs_match_literal(case):
+    # property-based: hypothesis searches edge sets (and shrinks any failure
+    # to a smallest graph); derandomized, so every run checks the same cases
+    n, edges, e = case
+    _same(inputs.from_edges(n, edges), e)
 
 
 @pytest.mark.parametrize("seed", range(40))
