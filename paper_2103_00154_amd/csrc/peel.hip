@@ -1089,11 +1089,24 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
                 }
             }
         } else {
+            // bin b's region is [bin_start[b], bin_start[b + 1]): the degrees
+            // of its survivors, which bound its records for a symmetric CSR.
+            // Records past the end (a survivor named by more rows than its
+            // degree: no valid input) are dropped and the pass is reported
+            // as an invariant violation.  Every bound is at most 2m < 2^31
+            // and a cursor moves by at most 2m per pass, so the unsigned
+            // comparison also rejects a cursor that wrapped past INT32_MAX.
+            const int32_t* __restrict__ bstart = w.bin_start;
 #pragma unroll
             for (int j = 0; j < kWalkItems; ++j) {
                 if (rk[j] >= 0) {
-                    const int32_t at = atomicAdd(&bin_cur[rk[j] >> kBinShift], 1);
-                    recs[at] = (uint16_t)(rk[j] & (kBinWidth - 1));
+                    const int32_t b = rk[j] >> kBinShift;
+                    const int32_t at = atomicAdd(&bin_cur[b], 1);
+                    if ((uint32_t)at < (uint32_t)bstart[b + 1]) {
+                        recs[at] = (uint16_t)(rk[j] & (kBinWidth - 1));
+                    } else {
+                        st->status = kStInvariant;
+                    }
                     ++cross;
                 }
             }

@@ -96,6 +96,106 @@ def test_sampled_six_and_seven_vertex_graphs_match_literal():
             _same(g, rnd.choice(EPS))
 
 
+def _literal_all(n, eps_num, eps_den):
+    """Definition 1 and Algorithm 1 over every labelled graph on n vertices
+    at once: graph i has edge j of itertools.combinations(range(n), 2) iff
+    bit j of i is set.  Every pass recounts deg_S(v) = |N(v) & S| and |E(S)|
+    from the edge bits (no running counts).  Returns per-graph arrays."""
+    pairs = list(itertools.combinations(range(n), 2))
+    G = 1 << len(pairs)
+    gid = np.arange(G, dtype=np.int64)
+    has = np.stack([(gid >> j) & 1 for j in range(len(pairs))]).astype(bool)  # [pair, graph]
+    inS = np.ones((n, G), dtype=bool)
+
+    def deg_in(members):  # |N(v) & members| for every v, every graph
+        d = np.zeros((n, G), dtype=np.int64)
+        for j, (u, v) in enumerate(pairs):
+            d[u] += has[j] & members[v]
+            d[v] += has[j] & members[u]
+        return d
+
+    def edges_in(members):
+        e = np.zeros(G, dtype=np.int64)
+        for j, (u, v) in enumerate(pairs):
+            e += has[j] & members[u] & members[v]
+        return e
+
+    removed_at = np.full((n, G), oracle.NEVER, dtype=np.int64)
+    best_e, best_v = edges_in(inS), np.full(G, n, dtype=np.int64)
+    best_pass = np.zeros(G, dtype=np.int64)
+    passes = np.zeros(G, dtype=np.int64)
+    trace = []  # per pass: dict of [graph] arrays (entries of finished graphs unused)
+    for k in range(1, n + 1):
+        live = inS.any(axis=0)
+        if not live.any():
+            break
+        V = inS.sum(axis=0)
+        E = edges_in(inS)
+        d = deg_in(inS)
+        failed = inS & (d * V * eps_den <= 2 * (eps_num + eps_den) * E)
+        nxt = inS & ~failed
+        E_next = edges_in(nxt)
+        full = deg_in(np.ones((n, G), dtype=bool))
+        trace.append({
+            "s_in": V, "e_in": E,
+            "thresh": np.where(V > 0, (2 * (eps_num + eps_den) * E) // np.maximum(V * eps_den, 1), 0),
+            "removed": failed.sum(axis=0),
+            "cross": (deg_in(nxt) * failed).sum(axis=0),
+            "intra": (deg_in(failed) * failed).sum(axis=0),
+            "scanned": (full * failed).sum(axis=0),
+            "s_out": nxt.sum(axis=0), "e_out": E_next, "live": live})
+        removed_at[failed] = k
+        passes[live] = k
+        V_next = nxt.sum(axis=0)
+        better = live & (V_next > 0) & (E_next * best_v > best_e * V_next)
+        best_e = np.where(better, E_next, best_e)
+        best_v = np.where(better, V_next, best_v)
+        best_pass = np.where(better, k, best_pass)
+        inS = nxt
+    return {"passes": passes, "best_pass": best_pass, "num": best_e, "den": best_v,
+            "removed_at": removed_at, "trace": trace, "pairs": pairs}
+
+
+def test_vectorised_literal_equals_the_literal_oracle():
+    # the all-graphs form of the literal oracle against its plain form
+    for n in (3, 4):
+        for e in EPS:
+            a = _literal_all(n, *e)
+            pairs = a["pairs"]
+            for i in range(1 << len(pairs)):
+                lit = literal.peel_literal(n, [p for j, p in enumerate(pairs) if i >> j & 1], *e)
+                assert (lit["passes"], lit["best_pass"], lit["num"], lit["den"]) == (
+                    a["passes"][i], a["best_pass"][i], a["num"][i], a["den"][i])
+                assert lit["removed_at"] == a["removed_at"][:, i].tolist()
+                for k, t in enumerate(lit["trace"]):
+                    for f, v in t.items():
+                        assert a["trace"][k][f][i] == v, (n, e, i, k, f)
+
+
+@pytest.mark.parametrize("e", EPS)
+def test_exhaustive_six_vertex_graphs_match_literal(e):
+    # every labelled graph on six vertices (2^15 of them), C oracle against
+    # the literal restatement, every field and every pass
+    n = 6
+    a = _literal_all(n, *e)
+    pairs = a["pairs"]
+    rows = [[u for u in range(n) if u != v] for v in range(n)]
+    pair_index = {p: j for j, p in enumerate(pairs)}
+    for i in range(1 << len(pairs)):
+        rp, ci = [0], []
+        for v in range(n):
+            ci += [u for u in rows[v] if i >> pair_index[(min(u, v), max(u, v))] & 1]
+            rp.append(len(ci))
+        c = oracle.peel(np.array(rp, np.int32), np.array(ci, np.int32), n, *e)
+        assert (c.passes, c.best_pass, c.num, c.den) == (
+            a["passes"][i], a["best_pass"][i], a["num"][i], a["den"][i]), (e, i)
+        assert c.removed_at.tolist() == a["removed_at"][:, i].tolist(), (e, i)
+        assert c.best.tolist() == [v for v in range(n) if a["removed_at"][v, i] > c.best_pass]
+        for k, t in enumerate(c.trace):
+            for f, v in t.items():
+                assert a["trace"][k][f][i] == v, (e, i, k, f)
+
+
 @st.composite
 def _hyp_graphs(draw, max_n=12):
     """A graph on 1..max_n vertices with any edge set (each possible edge
