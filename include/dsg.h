@@ -375,6 +375,48 @@ int32_t dsg_batch_run(const dsg_batch_plan* plan, const int32_t* row_ptr, const 
                       int32_t* best_ids, int32_t* removed_at, dsg_batch_result* results,
                       void* stream);
 
+/* ------------------------------------------------------------------------
+ * Peeling without the host.
+ * ------------------------------------------------------------------------ */
+
+/*
+ * dsg_peel without the host: every pass of Algorithm 1 (Section 3.1) runs
+ * in device work enqueued on `stream` up front, and the call returns once
+ * it is enqueued.  No host synchronisation, no allocation and no host
+ * memory: the call can be captured into a HIP graph and replayed.
+ *
+ * The loop "while |V| > 0" runs on the device: the first passes are the
+ * seven kernels of dsg_peel, each becoming a no-op once the graph is empty
+ * (16 of them, or launch->pass_batch when set, at most the pass bound);
+ * if the pass bound allows more, one workgroup then runs every remaining
+ * pass in a device loop until the graph is empty (or the watchdog or an
+ * invariant stops it).  Results equal dsg_peel's.
+ *
+ *   g, n, m, eps_num, eps_den, best_ids, removed_at
+ *               as for dsg_peel_ex (best_ids and removed_at may be NULL).
+ *   result      device, one dsg_batch_result (the struct of a batch's
+ *               per-graph result): written by the last kernel of the call
+ *               with status DSG_OK, DSG_EINVAL (row_ptr outside the CSR
+ *               contract) or DSG_EINTERNAL (watchdog or invariant), the
+ *               density (|E(S~)|, |S~|; 0 unless DSG_OK), passes, best pass
+ *               and the number of ids in best_ids.
+ *   launch      host or NULL: grid overrides as for dsg_peel_ex;
+ *               pass_batch is the number of passes enqueued as kernels
+ *               (>= 1); flags as for dsg_peel_ex except that no progress is
+ *               ever posted.
+ *   workspace   device, at least dsg_workspace_bytes(n, m) bytes, 256-byte
+ *               aligned (required: the call allocates nothing).  It must
+ *               not be used by other work until the enqueued work is done.
+ *
+ * Returns DSG_OK once enqueued; DSG_EINVAL / DSG_EOVERFLOW for the argument
+ * errors of dsg_peel plus a NULL result or workspace; DSG_EDEVICE if a
+ * launch fails.  Problems the device finds are reported in *result.
+ */
+int32_t dsg_peel_async(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num,
+                       int64_t eps_den, int32_t* best_ids, int32_t* removed_at,
+                       dsg_batch_result* result, const dsg_launch* launch,
+                       void* workspace, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

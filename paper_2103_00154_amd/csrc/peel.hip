@@ -1416,6 +1416,288 @@ __global__ __launch_bounds__(kBlock) void k_cbds_pairs(Work w, const int32_t* __
     }
 }
 
+// ============================================================ device tail
+// The passes of a peel that the host did not enqueue as kernels: one
+// workgroup runs Algorithm 1's loop (Section 3.1) on the device until the
+// graph is empty, the pass watchdog trips or an invariant fails.  Each pass
+// is the same step sequence as the seven-kernel pass, with workgroup
+// barriers in place of kernel boundaries:
+//
+//   copy     when the previous pass set the best graph, its survivor list
+//            (this pass's live list, ascending) becomes S~;
+//   mark     every live vertex with degree <= T_k fails (removal pass,
+//            live bit cleared); a stable compaction writes the survivors
+//            (id, degree) and the walk list (row start, prefix of row
+//            lengths) of the failures with degree > 0;
+//   ranks    the rank directory of the survivors (first rank per 32-vertex
+//            word);
+//   walk     the walk list's entries in tiles of kTailTile: every entry
+//            whose neighbour survives decrements that survivor's degree
+//            (one device atomic);
+//   finish   |V|, |E| = |E| - cross - intra / 2, the best graph (strict),
+//            the next threshold, the watchdog, the trace record.
+//
+// Data that another thread of the workgroup wrote in this kernel (lists,
+// degrees, the rank directory, the walk list) is read with L1-bypassing
+// loads, and degrees and live bits are changed with device atomics.
+
+constexpr int kTailBlock = 1024;
+constexpr int kTailWaves = kTailBlock / 64;
+constexpr int kTailItems = 8;                       // walk entries per thread and tile
+constexpr int kTailTile = kTailBlock * kTailItems;  // walk entries per tile
+
+__device__ inline int32_t ld_co(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint2 ld_co(const uint2* p) {
+    const unsigned long long x = __hip_atomic_load(
+        reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
+        __HIP_MEMORY_SCOPE_AGENT);
+    return make_uint2((uint32_t)x, (uint32_t)(x >> 32));
+}
+
+// Last index i in [lo, hi) with aoff[i] <= target, given aoff[lo] <= target
+// and aoff strictly increasing (every walked row has an entry).  Run by one
+// whole wave: each round probes 64 evenly spaced rows at once.
+__device__ inline int32_t wave_find_row(const int32_t* aoff, int32_t lo32, int32_t hi32,
+                                        int32_t target) {
+    const int lane = lane_id();
+    int64_t lo = lo32, hi = hi32;
+    while (hi - lo > 1) {
+        const int64_t step = (hi - lo + 63) / 64;
+        const int64_t probe = lo + (int64_t)lane * step;
+        const bool ok = probe < hi && ld_co(aoff + probe) <= target;
+        const int k = (int)__popcll(__ballot(ok)) - 1;  // ok lanes are a prefix; lane 0 is ok
+        lo = lo + (int64_t)max(k, 0) * step;
+        hi = min(hi, lo + step);
+    }
+    return (int32_t)lo;
+}
+
+__global__ __launch_bounds__(kTailBlock) void k_tail(Work w, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ ci, int64_t n,
+                                                     int64_t nnz, int32_t* __restrict__ best) {
+    DevState* st = w.st;
+    const int tid = threadIdx.x;
+    __shared__ uint32_t red32[kTailWaves];
+    __shared__ unsigned long long red64[kTailWaves];
+    __shared__ int32_t s_aoff[kTailTile + 1], s_arow[kTailTile + 1];
+    __shared__ int32_t s_r0, s_r1;
+    __shared__ int32_t s_pass, s_T, s_done, s_best_pass;
+    __shared__ int64_t s_S;
+    if (tid == 0) {
+        s_done = st->done;
+        s_pass = st->pass;
+        s_T = st->T;
+        s_S = st->S;
+        s_best_pass = st->best_pass;
+    }
+    __syncthreads();
+    while (!s_done) {
+        const int32_t pass = s_pass;
+        const int32_t T = s_T;
+        const int64_t S = s_S;
+        const int32_t* L = live_in(w, pass);  // pass >= 2: pass 1 always runs as kernels
+        int32_t* D = deg_in(w, pass);
+        int32_t* Lo = live_out(w, pass);
+        int32_t* Do = deg_out(w, pass);
+
+        // copy: S~ is the survivor list of the previous pass
+        if (best && s_best_pass == pass - 1) {
+            for (int64_t i = tid; i < S; i += kTailBlock) best[i] = ld_co(L + i);
+            if (tid == 0) st->best_count = S;
+        }
+
+        // mark and stable compaction, one live-list entry per thread and round
+        int64_t offL = 0, offA = 0, offE = 0;
+        unsigned long long sumF = 0;  // degrees of the failures
+        for (int64_t c0 = 0; c0 < S; c0 += kTailBlock) {
+            const int64_t i = c0 + tid;
+            int32_t v = -1, d = 0, len = 0;
+            if (i < S) {
+                v = ld_co(L + i);
+                d = ld_co(D + i);
+                if ((uint64_t)(int64_t)v >= (uint64_t)n) v = -1;
+            }
+            const bool fail = v >= 0 && d <= T;
+            const bool walk = fail && d > 0;
+            if (walk) len = rp[v + 1] - rp[v];
+            if (fail) {
+                w.removed_at[v] = pass;
+                atomicAnd(&w.dir[v >> 5].x, ~(1u << (v & 31)));
+                sumF += (unsigned long long)(int64_t)d;
+            }
+            uint32_t tot_la, tot_e;
+            const uint32_t ex_la = block_excl_sum<uint32_t, kTailWaves>(
+                (v >= 0 && !fail ? 1u : 0u) | (walk ? 1u << 16 : 0u), red32, &tot_la);
+            const uint32_t ex_e = block_excl_sum<uint32_t, kTailWaves>((uint32_t)len, red32, &tot_e);
+            if (v >= 0 && !fail) {
+                const int64_t p = offL + (ex_la & 0xFFFFu);
+                if (p < n) {
+                    Lo[p] = v;
+                    Do[p] = d;
+                }
+            } else if (walk) {
+                const int64_t p = offA + (ex_la >> 16);
+                if (p < n) {
+                    w.arow[p] = rp[v];
+                    w.aoff[p] = (int32_t)(offE + ex_e);
+                }
+            }
+            offL += tot_la & 0xFFFFu;
+            offA += tot_la >> 16;
+            offE += tot_e;
+        }
+        const int64_t nL = offL, nA = offA, E_walk = offE;
+        sumF = block_sum<unsigned long long, kTailWaves>(sumF, red64);
+
+        // rank directory: the first survivor of every 32-vertex word
+        for (int64_t r = tid; r < nL; r += kTailBlock) {
+            const int32_t v = ld_co(Lo + r);
+            const int32_t pv = r > 0 ? ld_co(Lo + r - 1) : -1;
+            if (r == 0 || (pv >> 5) != (v >> 5)) w.dir[v >> 5].y = (uint32_t)r;
+        }
+        __syncthreads();
+
+        // walk (nothing to decrement when no vertex survives)
+        unsigned long long cross = 0;
+        const int32_t* __restrict__ aoff = w.aoff;
+        const int32_t* __restrict__ arow = w.arow;
+        int32_t rlo = 0;
+        for (int64_t t0 = 0; nL > 0 && t0 < E_walk; t0 += kTailTile) {
+            const int32_t tlen = (int32_t)min<int64_t>(kTailTile, E_walk - t0);
+            if (tid < 64) {
+                const int32_t r0 = wave_find_row(aoff, rlo, (int32_t)nA, (int32_t)t0);
+                const int32_t r1 = wave_find_row(aoff, r0, (int32_t)nA, (int32_t)(t0 + tlen - 1));
+                if (tid == 0) {
+                    s_r0 = r0;
+                    s_r1 = r1;
+                }
+            }
+            __syncthreads();
+            // at most tlen rows: every walked row has an entry (its degree, at
+            // most its length, is positive), so row starts strictly increase
+            const int32_t r0 = s_r0, nr = min(s_r1 - s_r0 + 1, kTailTile + 1);
+            for (int32_t k = tid; k < nr; k += kTailBlock) {
+                s_aoff[k] = ld_co(aoff + r0 + k);
+                s_arow[k] = ld_co(arow + r0 + k);
+            }
+            __syncthreads();
+            for (int32_t k = tid; k < tlen; k += kTailBlock) {
+                const int32_t e = (int32_t)t0 + k;
+                int32_t lo = 0, hi = nr;  // last row with s_aoff <= e
+                while (hi - lo > 1) {
+                    const int32_t mid = (lo + hi) >> 1;
+                    if (s_aoff[mid] <= e) lo = mid; else hi = mid;
+                }
+                const int64_t pos = min<int64_t>((int64_t)s_arow[lo] + (e - s_aoff[lo]), nnz - 1);
+                const int32_t u = ci[pos];
+                if ((uint64_t)(int64_t)u < (uint64_t)n) {
+                    const uint2 dw = ld_co(w.dir + (u >> 5));
+                    const uint32_t bit = 1u << (u & 31);
+                    if (dw.x & bit) {
+                        const uint32_t rank = dw.y + __popc(dw.x & (bit - 1u));
+                        if ((int64_t)rank < nL)
+                            __hip_atomic_fetch_sub(Do + rank, 1, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                        ++cross;
+                    }
+                }
+            }
+            rlo = s_r1;
+            __syncthreads();  // s_aoff / s_arow are restaged for the next tile
+        }
+        cross = block_sum<unsigned long long, kTailWaves>(cross, red64);
+
+        // finish (one thread), as the seven-kernel pass does
+        if (tid == 0) {
+            const int64_t S_in = S, E_in = st->E, S_out = nL;
+            const int64_t intra = (int64_t)sumF - (int64_t)cross;
+            const int64_t E_out = E_in - (int64_t)cross - intra / 2;
+            int32_t done = 0;
+            if (st->status != kStOk || intra < 0 || (intra & 1) || E_out < 0 ||
+                (S_out == 0 && E_out != 0)) {
+                if (st->status == kStOk) st->status = kStInvariant;
+                done = 1;
+            } else {
+                if (pass <= st->trace_cap) {
+                    PassRecord r;
+                    r.s_in = S_in;
+                    r.e_in = E_in;
+                    r.thresh = T;
+                    r.removed = S_in - S_out;
+                    r.cross = (int64_t)cross;
+                    r.intra = intra;
+                    r.walked = S_out > 0 ? E_walk : 0;
+                    r.s_out = S_out;
+                    r.e_out = E_out;
+                    w.trace[pass - 1] = r;
+                }
+                st->tot_walked += S_out > 0 ? E_walk : 0;
+                st->tot_cross += (int64_t)cross;
+                st->tot_live += S_in;
+                st->tot_alist += nA;
+                if (S_out > 0 && E_out * st->best_S > st->best_E * S_out) {
+                    st->best_E = E_out;
+                    st->best_S = S_out;
+                    st->best_pass = pass;
+                }
+                st->S = S_out;
+                st->E = E_out;
+                st->nL = S_out;
+                if (S_out == 0) {
+                    done = 1;
+                } else if (pass + 1 > st->max_pass) {
+                    st->status = kStWatchdog;
+                    done = 1;
+                } else {
+                    st->T = pass_threshold(E_out, S_out, st->eps_num, st->eps_den);
+                    st->pass = pass + 1;
+                }
+            }
+            if (done) st->done = 1;
+            s_done = done;
+            s_pass = st->pass;
+            s_T = st->T;
+            s_S = st->S;
+            s_best_pass = st->best_pass;
+        }
+        __syncthreads();
+    }
+}
+
+// The device result of dsg_peel_async for the graph with no vertex.
+__global__ void k_async_empty(dsg_batch_result* out) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    dsg_batch_result r;
+    r.dens_num = r.dens_den = r.best_size = 0;
+    r.passes = r.best_pass = 0;
+    r.status = DSG_OK;
+    r.reserved = 0;
+    *out = r;
+}
+
+// The device result of a peel whose passes all ran without the host
+// (dsg_peel_async): the status, the density of S~ and the pass counts.
+__global__ void k_async_result(Work w, dsg_batch_result* out, int32_t extracted) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const DevState* st = w.st;
+    int32_t status = DSG_OK;
+    if (!st->done) status = DSG_EINTERNAL;  // cannot happen: the tail runs to the end
+    else if (st->status == kStBadRowPtr) status = DSG_EINVAL;
+    else if (st->status != kStOk) status = DSG_EINTERNAL;
+    else if (extracted && st->best_count != st->best_S) status = DSG_EINTERNAL;
+    dsg_batch_result r;
+    r.dens_num = status == DSG_OK ? st->best_E : 0;
+    r.dens_den = status == DSG_OK ? st->best_S : 0;
+    r.passes = st->pass;
+    r.best_pass = st->best_pass;
+    r.best_size = status == DSG_OK && extracted ? st->best_S : 0;
+    r.status = status;
+    r.reserved = 0;
+    *out = r;
+}
+
 // ================================================================== host
 
 namespace {
@@ -1592,7 +1874,7 @@ using namespace dsg;
 
 extern "C" {
 
-int32_t dsg_version(void) { return 1; }
+int32_t dsg_version(void) { return 2; }
 
 const char* dsg_strerror(int32_t status) {
     switch (status) {
@@ -1614,6 +1896,93 @@ size_t dsg_workspace_bytes(int64_t n, int64_t m) {
 }  // extern "C"
 
 namespace {
+
+// Pointers of a workspace laid out by layout(n, m); removed_at is the
+// caller's array when given.
+Work make_work(char* base, const Layout& L, int32_t* removed_at) {
+    Work w;
+    w.st = (DevState*)(base + L.st);
+    w.removed_at = removed_at ? removed_at : (int32_t*)(base + L.rem);
+    w.dir = (uint2*)(base + L.dir);
+    w.list0 = (int32_t*)(base + L.l0);
+    w.list1 = (int32_t*)(base + L.l1);
+    w.deg0 = (int32_t*)(base + L.d0);
+    w.deg1 = (int32_t*)(base + L.d1);
+    w.arow = (int32_t*)(base + L.arow);
+    w.aoff = (int32_t*)(base + L.aoff);
+    w.tile_first = (int32_t*)(base + L.tfirst);
+    w.tiles = (int4*)(base + L.tiles);
+    w.bin_start = (int32_t*)(base + L.bstart);
+    w.bin_cur = (int32_t*)(base + L.bcur);
+    w.bin_items = (int2*)(base + L.bitems);
+    w.items = (int4*)(base + L.items);
+    w.partial = (int32_t*)(base + L.partial);
+    w.recs = (uint16_t*)(base + L.recs);
+    w.toff = (uint16_t*)(base + L.toff);
+    w.filt = (uint32_t*)(base + L.filt);
+    w.wpart = (unsigned long long*)(base + L.wpart);
+    w.trace = (PassRecord*)(base + L.trace);
+    w.progress = nullptr;
+    return w;
+}
+
+// Grid sizes of one peel's kernels.
+struct Grids {
+    unsigned mark, walk, init, apply, reduce;
+};
+
+Grids default_grids(const DevInfo& di, int64_t n, int64_t m, const dsg_launch* launch) {
+    Grids gr;
+    const int64_t mt = mark_tiles(n) - 1;
+    const int64_t wt = std::max<int64_t>(walk_tiles(m) - 1, 1);
+    const int64_t mg = launch && launch->mark_grid ? launch->mark_grid : (int64_t)di.cus * 8;
+    const int64_t wg = launch && launch->walk_grid ? launch->walk_grid
+                                                   : (int64_t)di.cus * di.walk_blocks_per_cu;
+    gr.mark = (unsigned)std::max<int64_t>(1, std::min(mg, mt));
+    gr.walk = (unsigned)std::max<int64_t>(1, std::min({wg, wt, (int64_t)kMaxWalkGrid}));
+    gr.init = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>((int64_t)di.cus * 8, (n + kBlock - 1) / kBlock));
+    gr.apply = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>((int64_t)di.cus * di.apply_blocks_per_cu, max_items(n, m)));
+    gr.reduce = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>((int64_t)di.cus * 8, (n * 16 + kBlock - 1) / kBlock));
+    return gr;
+}
+
+hipError_t launch_init(const Work& w, const dsg_csr* g, int64_t n, int64_t m, int64_t num,
+                       int64_t den, int32_t max_pass, int32_t trace_cap,
+                       const dsg_launch* launch, int32_t core_mode, hipStream_t s) {
+    k_init_state<<<1, 64, 0, s>>>(w, g->row_ptr, n, m, num, den, max_pass,
+                                  std::min(trace_cap, kTraceCap), (int32_t)part_stride(n),
+                                  (int32_t)max_items(n, m),
+                                  launch && (launch->flags & DSG_LAUNCH_BIN_REGIONS) ? 1 : 0,
+                                  core_mode);
+    return hipGetLastError();
+}
+
+// One pass of Algorithm 1 as seven launches; `seq` numbers it for the
+// progress word (when w.progress is set).  `log` brackets the kernel groups
+// with events when it is on.
+hipError_t enqueue_pass(const Work& w, const Grids& gr, const dsg_csr* g, int64_t n, int64_t m,
+                        int32_t* best, hipStream_t s, EventLog& log, int64_t seq) {
+    hipError_t e = log.begin(kKindMark);
+    if (e != hipSuccess) return e;
+    k_mark_count<<<gr.mark, kBlock, 0, s>>>(w, g->row_ptr, n, best);
+    k_scan_tiles<<<1, kScanBlock, 0, s>>>(w, 0, n, seq);
+    k_mark_scatter<<<gr.mark, kBlock, 0, s>>>(w, g->row_ptr, n, walk_tiles(m), max_bins(n));
+    if ((e = hipGetLastError()) != hipSuccess || (e = log.end()) != hipSuccess ||
+        (e = log.begin(kKindWalk)) != hipSuccess)
+        return e;
+    k_walk<<<gr.walk, kBlock, 0, s>>>(w, g->col_idx, (uint32_t)n, (uint32_t)(2 * m));
+    if ((e = hipGetLastError()) != hipSuccess || (e = log.end()) != hipSuccess ||
+        (e = log.begin(kKindApply)) != hipSuccess)
+        return e;
+    k_walk_finish<<<1, kBlock, 0, s>>>(w, (int32_t)gr.walk);
+    k_apply<<<gr.apply, kApplyBlock, 0, s>>>(w);
+    k_reduce<<<gr.reduce, kBlock, 0, s>>>(w);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return log.end();
+}
 
 // The peel (core_mode 0) or CBDS-P (core_mode 1: k-core levels, then the
 // legitimate-vertex extension, reported in *cb).
@@ -1650,8 +2019,6 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
     int32_t max_pass, batch;
     int64_t launched = 0;
     unsigned mark_grid, walk_grid, init_grid, apply_grid, reduce_grid;
-    const int64_t nbins_cap = max_bins(n);
-    const int64_t items_cap = max_items(n, m);
 
     DSG_HIP(device_info(&di));
     if (!t_host_state) {
@@ -1668,81 +2035,31 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
         DSG_HIP(hipMalloc((void**)&base, L.total));
         owned = true;
     }
-    w.st = (DevState*)(base + L.st);
-    w.removed_at = removed_at ? removed_at : (int32_t*)(base + L.rem);
-    w.dir = (uint2*)(base + L.dir);
-    w.list0 = (int32_t*)(base + L.l0);
-    w.list1 = (int32_t*)(base + L.l1);
-    w.deg0 = (int32_t*)(base + L.d0);
-    w.deg1 = (int32_t*)(base + L.d1);
-    w.arow = (int32_t*)(base + L.arow);
-    w.aoff = (int32_t*)(base + L.aoff);
-    w.tile_first = (int32_t*)(base + L.tfirst);
-    w.tiles = (int4*)(base + L.tiles);
-    w.bin_start = (int32_t*)(base + L.bstart);
-    w.bin_cur = (int32_t*)(base + L.bcur);
-    w.bin_items = (int2*)(base + L.bitems);
-    w.items = (int4*)(base + L.items);
-    w.partial = (int32_t*)(base + L.partial);
-    w.recs = (uint16_t*)(base + L.recs);
-    w.toff = (uint16_t*)(base + L.toff);
-    w.filt = (uint32_t*)(base + L.filt);
-    w.wpart = (unsigned long long*)(base + L.wpart);
-    w.trace = (PassRecord*)(base + L.trace);
-    w.progress = nullptr;
+    w = make_work(base, L, removed_at);
 
     // core levels: every pass removes a vertex or ends a level, and every
     // level after the first removes a vertex, so 2n + 1 passes suffice
     max_pass = core_mode ? (int32_t)std::min<int64_t>(2 * n + 2, INT32_MAX)
                          : pass_bound(n, eps_num, eps_den);
     {
-        const int64_t mt = mark_tiles(n) - 1;
-        const int64_t wt = std::max<int64_t>(walk_tiles(m) - 1, 1);
-        int64_t mg = launch && launch->mark_grid ? launch->mark_grid : (int64_t)di.cus * 8;
-        int64_t wg = launch && launch->walk_grid ? launch->walk_grid
-                                                 : (int64_t)di.cus * di.walk_blocks_per_cu;
-        mark_grid = (unsigned)std::max<int64_t>(1, std::min(mg, mt));
-        walk_grid = (unsigned)std::max<int64_t>(1, std::min({wg, wt, (int64_t)kMaxWalkGrid}));
-        init_grid = (unsigned)std::max<int64_t>(
-            1, std::min<int64_t>((int64_t)di.cus * 8, (n + kBlock - 1) / kBlock));
-        apply_grid = (unsigned)std::max<int64_t>(
-            1, std::min<int64_t>((int64_t)di.cus * di.apply_blocks_per_cu, items_cap));
-        reduce_grid = (unsigned)std::max<int64_t>(
-            1, std::min<int64_t>((int64_t)di.cus * 8, (n * 16 + kBlock - 1) / kBlock));
+        const Grids gr = default_grids(di, n, m, launch);
+        mark_grid = gr.mark;
+        walk_grid = gr.walk;
+        init_grid = gr.init;
+        apply_grid = gr.apply;
+        reduce_grid = gr.reduce;
         batch = launch && launch->pass_batch ? launch->pass_batch : std::min(max_pass, 8);
     }
 
     DSG_HIP(log.begin(kKindInit));
-    k_init_state<<<1, 64, 0, s>>>(w, g->row_ptr, n, m, eps_num, eps_den, max_pass,
-                                  std::min(trace_cap, kTraceCap), (int32_t)part_stride(n),
-                                  (int32_t)items_cap,
-                                  launch && (launch->flags & DSG_LAUNCH_BIN_REGIONS) ? 1 : 0,
-                                  core_mode);
-    DSG_HIP(hipGetLastError());
+    DSG_HIP(launch_init(w, g, n, m, eps_num, eps_den, max_pass, trace_cap, launch, core_mode, s));
     DSG_HIP(log.end());
 
     {  // the scope of pass_launches, which the error paths jump past
     // One pass, seven launches; `seq` numbers it for the progress word.
     auto pass_launches = [&](int64_t seq) -> hipError_t {
-        hipError_t e = log.begin(kKindMark);
-        if (e != hipSuccess) return e;
-        k_mark_count<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, n,
-                                                  core_mode ? nullptr : best_ids);
-        k_scan_tiles<<<1, kScanBlock, 0, s>>>(w, 0, n, seq);
-        k_mark_scatter<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, n, walk_tiles(m),
-                                                    nbins_cap);
-        if ((e = hipGetLastError()) != hipSuccess || (e = log.end()) != hipSuccess ||
-            (e = log.begin(kKindWalk)) != hipSuccess)
-            return e;
-        k_walk<<<walk_grid, kBlock, 0, s>>>(w, g->col_idx, (uint32_t)n, (uint32_t)(2 * m));
-        if ((e = hipGetLastError()) != hipSuccess || (e = log.end()) != hipSuccess ||
-            (e = log.begin(kKindApply)) != hipSuccess)
-            return e;
-        k_walk_finish<<<1, kBlock, 0, s>>>(w, (int32_t)walk_grid);
-        k_apply<<<apply_grid, kApplyBlock, 0, s>>>(w);
-        k_reduce<<<reduce_grid, kBlock, 0, s>>>(w);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        return log.end();
+        const Grids gr{mark_grid, walk_grid, init_grid, apply_grid, reduce_grid};
+        return enqueue_pass(w, gr, g, n, m, core_mode ? nullptr : best_ids, s, log, seq);
     };
 
     // Peeling passes run one pass ahead of the host: pass k's tile scan
@@ -1895,6 +2212,65 @@ done:
 
 }  // namespace
 
+namespace dsg {
+
+// Passes the host enqueues as kernels before the device tail takes over in
+// dsg_peel_async.  A peel that needs more passes runs them in k_tail.
+constexpr int32_t kAsyncHead = 16;
+
+// dsg_peel_async (declared in host.h for the entry point that brings its own
+// workspace): init, `head` passes of seven launches (each a no-op once
+// the graph is empty), the device tail when the watchdog allows more passes,
+// extraction and the device result.  Launch counts are fixed in advance, so
+// nothing waits for the device.
+int32_t peel_async(const dsg_csr* g, int64_t n, int64_t m, int64_t num, int64_t den,
+                  int32_t* best_ids, int32_t* removed_at, dsg_batch_result* result,
+                  const dsg_launch* launch, void* workspace, size_t ws_bytes, void* stream) {
+    if (!g || !result) return DSG_EINVAL;
+    const int32_t rc = check_sizes(n, m, num, den);
+    if (rc != DSG_OK) return rc;
+    if (n > 0 && !g->row_ptr) return DSG_EINVAL;
+    if (m > 0 && !g->col_idx) return DSG_EINVAL;
+    if (m > 0 && n < 2) return DSG_EINVAL;
+    if (launch && (launch->mark_grid < 0 || launch->walk_grid < 0 || launch->pass_batch < 0))
+        return DSG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {
+        k_async_empty<<<1, 64, 0, s>>>(result);
+        const hipError_t e = hipGetLastError();
+        return e == hipSuccess ? DSG_OK : map_hip(e);
+    }
+    const Layout L = layout(n, m);
+    if (!workspace || ws_bytes < L.total || ((uintptr_t)workspace & 255u)) return DSG_EINVAL;
+    DevInfo di;
+    hipError_t e = device_info(&di);
+    if (e != hipSuccess) return map_hip(e);
+    const Work w = make_work((char*)workspace, L, removed_at);
+    const Grids gr = default_grids(di, n, m, launch);
+    const int32_t max_pass = pass_bound(n, num, den);
+    const int32_t want = launch && launch->pass_batch ? launch->pass_batch : kAsyncHead;
+    const int32_t head = std::max(1, std::min(max_pass, want));
+    EventLog log;  // off
+    e = launch_init(w, g, n, m, num, den, max_pass, kTraceCap, launch, 0, s);
+    for (int32_t p = 0; e == hipSuccess && p < head; ++p)
+        e = enqueue_pass(w, gr, g, n, m, best_ids, s, log, 0);
+    if (e == hipSuccess && head < max_pass) {
+        k_tail<<<1, kTailBlock, 0, s>>>(w, g->row_ptr, g->col_idx, n, 2 * m, best_ids);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && best_ids) {
+        k_extract_iota<<<gr.init, kBlock, 0, s>>>(w, n, best_ids);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        k_async_result<<<1, 64, 0, s>>>(w, result, best_ids ? 1 : 0);
+        e = hipGetLastError();
+    }
+    return e == hipSuccess ? DSG_OK : map_hip(e);
+}
+
+}  // namespace dsg
+
 extern "C" {
 
 int32_t dsg_peel_ex(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_t eps_den,
@@ -1912,6 +2288,14 @@ int32_t dsg_cbds(const dsg_csr* g, int64_t n, int64_t m, int32_t* best_ids, int3
     dsg_result r;
     return run_peel(g, n, m, 0, 1, 1, best_ids, core, &r, out, trace, trace_cap, nullptr,
                     nullptr, workspace, ws_bytes, stream);
+}
+
+int32_t dsg_peel_async(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num,
+                       int64_t eps_den, int32_t* best_ids, int32_t* removed_at,
+                       dsg_batch_result* result, const dsg_launch* launch, void* workspace,
+                       size_t ws_bytes, void* stream) {
+    return peel_async(g, n, m, eps_num, eps_den, best_ids, removed_at, result, launch, workspace,
+                      ws_bytes, stream);
 }
 
 int32_t dsg_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_t eps_den,

@@ -27,7 +27,7 @@ DSG_EINTERNAL = -5
 #: every symbol include/dsg.h declares
 EXPORTS = ("dsg_version", "dsg_strerror", "dsg_workspace_bytes", "dsg_peel", "dsg_peel_ex",
            "dsg_validate_csr", "dsg_cbds", "dsg_batch_workspace_bytes", "dsg_batch_prepare",
-           "dsg_batch_run")
+           "dsg_batch_run", "dsg_peel_async")
 
 TRACE_FIELDS = ("s_in", "e_in", "thresh", "removed", "cross", "intra", "walked", "s_out", "e_out")
 
@@ -138,6 +138,9 @@ def lib():
         h.dsg_batch_prepare.restype = _I32
         h.dsg_batch_run.argtypes = [ctypes.POINTER(BatchPlan), _P, _P, _P, _P, _P, _P]
         h.dsg_batch_run.restype = _I32
+        h.dsg_peel_async.argtypes = [ctypes.POINTER(CSR), _I64, _I64, _I64, _I64, _P, _P, _P, _P,
+                                     _P, _SZ, _P]
+        h.dsg_peel_async.restype = _I32
         _lib = h
     return _lib
 
@@ -439,3 +442,53 @@ class Batch:
                         "best_size": int(row[3]),
                         "status": int(np.int32(row[4] & 0xFFFFFFFF))})
         return out
+
+
+# --------------------------------------------------------------------------
+# peeling without the host
+# --------------------------------------------------------------------------
+
+def peel_async(row_ptr, col_idx, eps=(1, 10), *, workspace, m: int | None = None,
+               best_ids=None, removed_at=None, result=None, head_passes: int = 0,
+               stream=None):
+    """Enqueue dsg_peel_async: every pass runs on the device, nothing waits
+    for it and nothing is allocated by the library.  Returns the device
+    result tensor (int64, RESULT_WORDS words: one dsg_batch_result; read it
+    with :func:`async_result` after synchronising).  ``workspace`` is a
+    uint8 device tensor of at least :func:`workspace_bytes` bytes;
+    ``head_passes`` > 0 sets how many passes are enqueued as kernels before
+    the device loop takes over."""
+    import torch
+    _check_int32_cuda("row_ptr", row_ptr)
+    _check_int32_cuda("col_idx", col_idx)
+    n = row_ptr.numel() - 1
+    if m is None:
+        m = col_idx.numel() // 2
+    for name, t in (("best_ids", best_ids), ("removed_at", removed_at)):
+        if t is not None:
+            _check_int32_cuda(name, t)
+            if t.numel() < n:
+                raise ValueError(f"{name} needs n entries")
+    if workspace is None or not workspace.is_cuda:
+        raise TypeError("peel_async needs a device workspace")
+    if result is None:
+        result = torch.empty(RESULT_WORDS, dtype=torch.int64, device=row_ptr.device)
+    csr = CSR(row_ptr.data_ptr(), col_idx.data_ptr() if col_idx.numel() else None)
+    ln = Launch(0, 0, int(head_passes), 0) if head_passes else None
+    with torch.cuda.device(row_ptr.device):
+        rc = lib().dsg_peel_async(ctypes.byref(csr), n, m, int(eps[0]), int(eps[1]),
+                                  best_ids.data_ptr() if best_ids is not None else None,
+                                  removed_at.data_ptr() if removed_at is not None else None,
+                                  result.data_ptr(),
+                                  ctypes.byref(ln) if ln is not None else None,
+                                  workspace.data_ptr(),
+                                  workspace.numel() * workspace.element_size(),
+                                  _stream_handle(stream))
+    if rc != DSG_OK:
+        raise DsgError(rc, "dsg_peel_async")
+    return result
+
+
+def async_result(res) -> dict:
+    """Host dict of a device result written by dsg_peel_async."""
+    return Batch.results(res.reshape(1, RESULT_WORDS))[0]

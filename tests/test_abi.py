@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_strerror():
     h = dsg.lib()
-    assert h.dsg_version() == 1
+    assert h.dsg_version() == 2
     for code in (0, -1, -2, -3, -4, -5, -99):
         assert h.dsg_strerror(code)
 
@@ -252,3 +252,33 @@ def test_cbds_struct_and_argument_errors(tmp_path):
     assert h.dsg_cbds(ctypes.byref(csr), 0, 0, None, None, ctypes.byref(res), None, 0, None, 0,
                       None) == dsg.DSG_OK
     assert (res.dens_num, res.dens_den, res.passes) == (0, 0, 0)
+
+
+# ------------------------------------------------------------ peel_async
+
+def _async(n, m, num, den, rp=0x1000, ci=0x2000, res=0x3000, ws=0x100000, ws_len=1 << 30,
+           launch=None):
+    h = dsg.lib()
+    csr = dsg.CSR(rp, ci)
+    return h.dsg_peel_async(ctypes.byref(csr), n, m, num, den, None, None, res,
+                            ctypes.byref(launch) if launch is not None else None, ws, ws_len,
+                            None)
+
+
+# each case is rejected on the host before the library makes a HIP call
+@pytest.mark.parametrize("args,status", [
+    (dict(n=5, m=2, num=1, den=10, res=None), dsg.DSG_EINVAL),
+    (dict(n=5, m=2, num=1, den=10, ws=None), dsg.DSG_EINVAL),
+    (dict(n=5, m=2, num=1, den=10, ws_len=64), dsg.DSG_EINVAL),
+    (dict(n=5, m=2, num=1, den=10, ws=0x100001), dsg.DSG_EINVAL),
+    (dict(n=5, m=2, num=1, den=0), dsg.DSG_EINVAL),
+    (dict(n=5, m=2, num=-1, den=10), dsg.DSG_EINVAL),
+    (dict(n=5, m=2, num=1, den=10, rp=None), dsg.DSG_EINVAL),
+    (dict(n=5, m=2, num=1, den=10, ci=None), dsg.DSG_EINVAL),
+    (dict(n=1, m=1, num=1, den=10), dsg.DSG_EINVAL),
+    (dict(n=5, m=2, num=1, den=10, launch=dsg.Launch(0, 0, -1, 0)), dsg.DSG_EINVAL),
+    (dict(n=2**31, m=1, num=1, den=10), dsg.DSG_EOVERFLOW),
+    (dict(n=10, m=2**30, num=1, den=10), dsg.DSG_EOVERFLOW),
+])
+def test_peel_async_argument_errors_before_device_work(args, status):
+    assert _async(**args) == status

@@ -1,0 +1,256 @@
+"""dsg_peel_async on the GPU: Algorithm 1's pass loop (Section 3.1) with no
+host synchronisation, the result written to device memory.  Every output is
+compared with the oracle: passes, best pass, density, S~ and the removal
+pass of every vertex; the configurations ER 10k/50k, R-MAT scale 20 at three
+eps and R-MAT scale 24 + planted block; eagerly and replayed from a captured
+HIP graph.  The device loop that takes over after the first passes (one
+workgroup) is covered by forcing it to start after pass 1 or 2, on small and
+full-size graphs and on graphs that need hundreds of passes.  Inputs that
+break the CSR contract end with the documented status in the result (and,
+through dsg_peel, as DSG_EINTERNAL with bin regions forced).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import say, to_device
+from paper_2103_00154_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+_graphs = {}
+
+
+def _graph(name):
+    if name not in _graphs:
+        if name == "er10k":
+            _graphs[name] = inputs.erdos_renyi(10_000, 50_000, 0)
+        elif name == "rmat20":
+            _graphs[name] = inputs.rmat(20, 16, seed=0)
+        elif name == "rmat24":
+            _graphs.pop("rmat20", None)
+            _graphs[name] = inputs.rmat(24, 16, seed=0, planted=(2000, 0.5, 1))
+    return _graphs[name]
+
+
+def run_async(g, eps, head=0, rp=None, ci=None, ws=None):
+    import torch
+    from paper_2103_00154_amd import dsg
+    if rp is None:
+        rp, ci = to_device(g)
+    if ws is None:
+        ws = dsg.alloc_workspace(g.n, g.m)
+    best = torch.full((max(g.n, 1),), -7, dtype=torch.int32, device="cuda")
+    rem = torch.full((max(g.n, 1),), -7, dtype=torch.int32, device="cuda")
+    res = dsg.peel_async(rp, ci, eps, m=g.m, workspace=ws, best_ids=best, removed_at=rem,
+                         head_passes=head)
+    torch.cuda.synchronize()
+    return dsg.async_result(res), best, rem
+
+
+def assert_same(r, best, rem, o, n):
+    assert r["status"] == 0, r
+    assert (r["passes"], r["best_pass"], r["num"], r["den"], r["best_size"]) == (
+        o.passes, o.best_pass, o.num, o.den, len(o.best)), (r, o.passes, o.best_pass, o.num, o.den)
+    assert np.array_equal(best[:len(o.best)].cpu().numpy(), o.best)
+    assert np.array_equal(rem[:n].cpu().numpy(), o.removed_at[:n])
+
+
+def check(g, eps, head=0, o=None):
+    say(f"case {g.name} n={g.n} m={g.m} eps={eps[0]}/{eps[1]} head={head}")
+    r, best, rem = run_async(g, eps, head)
+    o = o if o is not None else oracle.peel_graph(g, *eps, trace=False)
+    assert_same(r, best, rem, o, g.n)
+    return r, o
+
+
+@pytest.mark.parametrize("name,eps", [("er10k", (1, 10)), ("rmat20", (1, 100)),
+                                      ("rmat20", (1, 10)), ("rmat20", (1, 1)),
+                                      ("rmat24", (1, 10))])
+def test_configs_against_the_oracle(name, eps):
+    g = _graph(name)
+    o = oracle.peel_graph(g, *eps, trace=False)
+    check(g, eps, o=o)
+    # the same with the device loop running every pass after the first two
+    check(g, eps, head=2, o=o)
+
+
+@pytest.mark.parametrize("name,eps", [("er10k", (1, 10)), ("rmat20", (1, 100)),
+                                      ("rmat20", (1, 10)), ("rmat20", (1, 1))])
+def test_captured_graph_replays_match_the_oracle(name, eps):
+    import torch
+    from paper_2103_00154_amd import dsg
+    g = _graph(name)
+    o = oracle.peel_graph(g, *eps, trace=False)
+    rp, ci = to_device(g)
+    ws = dsg.alloc_workspace(g.n, g.m)
+    best = torch.full((g.n,), -7, dtype=torch.int32, device="cuda")
+    rem = torch.full((g.n,), -7, dtype=torch.int32, device="cuda")
+    res = torch.zeros(dsg.RESULT_WORDS, dtype=torch.int64, device="cuda")
+    for head in (0, 1):
+        say(f"case {g.name} eps={eps[0]}/{eps[1]} captured, head={head}")
+        dsg.peel_async(rp, ci, eps, workspace=ws, best_ids=best, removed_at=rem, result=res,
+                       head_passes=head)  # eager run before capture
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        stream = torch.cuda.Stream()
+        with torch.cuda.graph(graph, stream=stream):
+            dsg.peel_async(rp, ci, eps, workspace=ws, best_ids=best, removed_at=rem, result=res,
+                           head_passes=head)
+        for rep in range(3):
+            best.fill_(-1)
+            rem.fill_(-1)
+            res.zero_()
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            assert_same(dsg.async_result(res), best, rem, o, g.n)
+            # eager work on the same workspace between replays
+            other = dsg.peel(rp, ci, (0, 1), workspace=ws)
+            torch.cuda.synchronize()
+            assert other.passes >= 1
+            say(f"replay {rep} ok")
+        del graph
+
+
+def test_capture_of_the_full_size_graph():
+    import torch
+    from paper_2103_00154_amd import dsg
+    g = _graph("rmat24")
+    o = oracle.peel_graph(g, 1, 10, trace=False)
+    rp, ci = to_device(g)
+    ws = dsg.alloc_workspace(g.n, g.m)
+    best = torch.full((g.n,), -7, dtype=torch.int32, device="cuda")
+    rem = torch.full((g.n,), -7, dtype=torch.int32, device="cuda")
+    res = torch.zeros(dsg.RESULT_WORDS, dtype=torch.int64, device="cuda")
+    dsg.peel_async(rp, ci, (1, 10), workspace=ws, best_ids=best, removed_at=rem, result=res)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=torch.cuda.Stream()):
+        dsg.peel_async(rp, ci, (1, 10), workspace=ws, best_ids=best, removed_at=rem,
+                       result=res)
+    for rep in range(2):
+        res.zero_()
+        best.fill_(-1)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert_same(dsg.async_result(res), best, rem, o, g.n)
+        say(f"rmat24 replay {rep} ok")
+
+
+def _tail_graphs():
+    yield inputs.from_edges(5, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3), (0, 4)])
+    yield inputs.from_edges(6, [(1, 4), (1, 5), (3, 4)])
+    yield inputs.from_edges(4, [(0, 2), (0, 3), (1, 3), (2, 3)])
+    yield inputs.empty(9)
+    yield inputs.clique(40)
+    yield inputs.path(3000)  # eps = 0: about 1500 passes
+    yield inputs.star(5000)
+    yield inputs.disjoint_cliques(30, 12)
+    yield inputs.erdos_renyi(20_000, 90_000, 3)
+    yield inputs.chung_lu(60_000, 20, 2.2, 4)
+    yield inputs.rmat(16, 16, seed=5)
+    yield inputs.rmat(14, 8, seed=6, planted=(300, 0.4, 7))
+
+
+@pytest.mark.parametrize("gi", range(12))
+def test_device_loop_from_pass_two(gi):
+    g = list(_tail_graphs())[gi]
+    for eps in ((0, 1), (1, 100), (1, 10), (3, 1)):
+        for head in (1, 3):
+            check(g, eps, head=head)
+
+
+def test_sampled_small_graphs_in_the_device_loop():
+    import random
+    import itertools
+    rnd = random.Random(17)
+    for _ in range(60):
+        n = rnd.randint(2, 12)
+        pairs = list(itertools.combinations(range(n), 2))
+        edges = [p for p in pairs if rnd.random() < rnd.choice([0.2, 0.5, 0.8])]
+        g = inputs.from_edges(n, edges)
+        check(g, rnd.choice([(0, 1), (1, 10), (1, 1)]), head=1)
+
+
+def test_empty_graph_and_head_above_the_bound():
+    import torch
+    from paper_2103_00154_amd import dsg
+    rp = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ci = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = dsg.alloc_workspace(0, 0)
+    res = dsg.peel_async(rp, ci, (1, 10), m=0, workspace=ws)
+    torch.cuda.synchronize()
+    r = dsg.async_result(res)
+    assert (r["status"], r["passes"], r["num"], r["den"], r["best_size"]) == (0, 0, 0, 0, 0)
+    g = inputs.erdos_renyi(2000, 9000, 5)
+    check(g, (1, 10), head=10_000)
+
+
+def _one_sided():
+    # vertices 1..10 list vertex 0, which lists only 1 and 2 (degree 2)
+    rp = np.array([0, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12], np.int32)
+    ci = np.array([1, 2] + [0] * 10, np.int32)
+    return rp, ci
+
+
+def test_contract_violations_reach_the_result():
+    import torch
+    from paper_2103_00154_amd import dsg
+    rp, ci = (torch.from_numpy(a).cuda() for a in _one_sided())
+    ws = dsg.alloc_workspace(11, 6)
+    for head in (0, 1):
+        r = dsg.async_result(dsg.peel_async(rp, ci, (1, 10), m=6, workspace=ws,
+                                            head_passes=head))
+        assert r["status"] == dsg.DSG_EINTERNAL, r
+    # row_ptr[n] != 2m
+    g = inputs.erdos_renyi(500, 2000, 1)
+    rpg, cig = to_device(g)
+    ws = dsg.alloc_workspace(g.n, g.m)
+    r = dsg.async_result(dsg.peel_async(rpg, cig, (1, 10), m=g.m - 1, workspace=ws))
+    assert r["status"] == dsg.DSG_EINVAL, r
+
+
+def test_one_sided_rows_with_bin_regions_are_an_internal_error():
+    # more decrement records for vertex 0 than its degree: with bin regions
+    # forced they overrun its region, are dropped, and the peel reports
+    # DSG_EINTERNAL (the kernels end normally); the per-tile layout reports
+    # the same through the edge count
+    import torch
+    from paper_2103_00154_amd import dsg
+    rp, ci = (torch.from_numpy(a).cuda() for a in _one_sided())
+    for launch in ({"bin_regions": True}, {"bin_regions": True, "pass_batch": 1}, None):
+        with pytest.raises(dsg.DsgError) as exc:
+            dsg.peel(rp, ci, (1, 10), m=6, launch=launch)
+        assert exc.value.status == dsg.DSG_EINTERNAL
+    # and the library still works afterwards
+    g = inputs.erdos_renyi(3000, 12000, 2)
+    r = dsg.peel(*to_device(g), (1, 10), launch={"bin_regions": True})
+    o = oracle.peel_graph(g, 1, 10, trace=False)
+    assert (r.passes, r.num, r.den) == (o.passes, o.num, o.den)
+
+
+def test_two_streams_with_their_own_workspaces():
+    import torch
+    from paper_2103_00154_amd import dsg
+    ga, gb = inputs.rmat(16, 16, seed=61), inputs.chung_lu(60_000, 20, 2.3, 62)
+    oa, ob = oracle.peel_graph(ga, 1, 10, trace=False), oracle.peel_graph(gb, 0, 1, trace=False)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    (rpa, cia), (rpb, cib) = to_device(ga), to_device(gb)
+    wa, wb = dsg.alloc_workspace(ga.n, ga.m), dsg.alloc_workspace(gb.n, gb.m)
+    ba = torch.empty(ga.n, dtype=torch.int32, device="cuda")
+    bb = torch.empty(gb.n, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    for _ in range(3):
+        with torch.cuda.stream(sa):
+            ra = dsg.peel_async(rpa, cia, (1, 10), workspace=wa, best_ids=ba, stream=sa)
+        with torch.cuda.stream(sb):
+            rb = dsg.peel_async(rpb, cib, (0, 1), workspace=wb, best_ids=bb, stream=sb)
+        torch.cuda.synchronize()
+        for r, b, o in ((ra, ba, oa), (rb, bb, ob)):
+            d = dsg.async_result(r)
+            assert (d["status"], d["passes"], d["num"], d["den"]) == (0, o.passes, o.num, o.den)
+            assert np.array_equal(b[:d["best_size"]].cpu().numpy(), o.best)
