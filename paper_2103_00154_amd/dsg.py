@@ -110,6 +110,13 @@ def lib():
     global _lib
     if _lib is None:
         path = _build.ensure_dsg()
+        # torch brings its own HIP runtime with the same soname as the one
+        # the library is linked against (libamdhip64.so.7); whichever is
+        # loaded first serves both.  torch goes first, so that the library
+        # and torch share one runtime: torch's device pointers and streams
+        # belong to it (loaded the other way round, the library's runtime
+        # finds no device).
+        import torch  # noqa: F401
         try:
             h = ctypes.CDLL(str(path))
         except OSError as exc:  # no silent fallback
