@@ -417,6 +417,27 @@ int32_t dsg_peel_async(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num,
                        dsg_batch_result* result, const dsg_launch* launch,
                        void* workspace, size_t ws_bytes, void* stream);
 
+/*
+ * dsg_peel_async for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same work and results as dsg_peel_async, with the workspace taken
+ * from a static device array of 256 MiB that the library holds on every
+ * GPU it runs on until the process ends.  The caller still passes the graph,
+ * best_ids, removed_at and the device result as for dsg_peel_async.
+ *
+ * The graph must fit the array: dsg_workspace_bytes(n, m) <= 256 MiB
+ * (about n = 2^20 vertices with m = 16 M edges); larger graphs return
+ * DSG_EINVAL.  Every call on one GPU uses that GPU's array, and the array
+ * keeps what the last call left (the peel initialises what it reads), so
+ * calls that overlap on one GPU (other streams, other threads) race: order
+ * them.  Allocates nothing; the first call on a device looks up the
+ * array's device address.  Errors as for dsg_peel_async.
+ */
+int32_t dsg_peel_async_noalloc(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num,
+                               int64_t eps_den, int32_t* best_ids, int32_t* removed_at,
+                               dsg_batch_result* result, const dsg_launch* launch,
+                               void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,7 @@ DSG_EINTERNAL = -5
 #: every symbol include/dsg.h declares
 EXPORTS = ("dsg_version", "dsg_strerror", "dsg_workspace_bytes", "dsg_peel", "dsg_peel_ex",
            "dsg_validate_csr", "dsg_cbds", "dsg_batch_workspace_bytes", "dsg_batch_prepare",
-           "dsg_batch_run", "dsg_peel_async")
+           "dsg_batch_run", "dsg_peel_async", "dsg_peel_async_noalloc")
 
 TRACE_FIELDS = ("s_in", "e_in", "thresh", "removed", "cross", "intra", "walked", "s_out", "e_out")
 
@@ -148,6 +148,9 @@ def lib():
         h.dsg_peel_async.argtypes = [ctypes.POINTER(CSR), _I64, _I64, _I64, _I64, _P, _P, _P, _P,
                                      _P, _SZ, _P]
         h.dsg_peel_async.restype = _I32
+        h.dsg_peel_async_noalloc.argtypes = [ctypes.POINTER(CSR), _I64, _I64, _I64, _I64, _P, _P,
+                                             _P, _P, _P]
+        h.dsg_peel_async_noalloc.restype = _I32
         _lib = h
     return _lib
 

@@ -282,3 +282,17 @@ def _async(n, m, num, den, rp=0x1000, ci=0x2000, res=0x3000, ws=0x100000, ws_len
 ])
 def test_peel_async_argument_errors_before_device_work(args, status):
     assert _async(**args) == status
+
+
+# each case is rejected on the host before the library makes a HIP call
+@pytest.mark.parametrize("n,m,num,den,res,status", [
+    (5, 2, 1, 10, None, dsg.DSG_EINVAL),
+    (5, 2, 1, 0, 0x3000, dsg.DSG_EINVAL),
+    (2**31, 1, 1, 10, 0x3000, dsg.DSG_EOVERFLOW),
+    (1 << 22, 1 << 25, 1, 10, 0x3000, dsg.DSG_EINVAL),  # workspace above the 256 MiB array
+])
+def test_peel_async_noalloc_argument_errors(n, m, num, den, res, status):
+    h = dsg.lib()
+    csr = dsg.CSR(0x1000, 0x2000)
+    assert h.dsg_peel_async_noalloc(ctypes.byref(csr), n, m, num, den, None, None, res, None,
+                                    None) == status
