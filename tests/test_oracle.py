@@ -256,6 +256,47 @@ def test_goldberg_matches_bruteforce(seed):
     assert len(members) == sg
 
 
+def _densest_union_bruteforce(n, edges):
+    """rho* and the union of every subset of density rho* (brute force)."""
+    adj = [0] * n
+    for u, v in edges:
+        adj[u] |= 1 << v
+        adj[v] |= 1 << u
+    best, union = (0, 1), 0
+    for mask in range(1, 1 << n):
+        size = bin(mask).count("1")
+        e = sum(bin(adj[v] & mask).count("1") for v in range(n) if mask >> v & 1) // 2
+        if e * best[1] > best[0] * size:
+            best, union = (e, size), mask
+        elif e * best[1] == best[0] * size:
+            union |= mask
+    return best, [v for v in range(n) if union >> v & 1]
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_maximal_densest_matches_bruteforce_union(seed):
+    rnd = random.Random(3000 + seed)
+    n = rnd.randint(1, 11)
+    g = inputs.random_small(n, rnd.choice([0.15, 0.3, 0.5, 0.9]), seed)
+    (eb, sb), union = _densest_union_bruteforce(n, _edges(g))
+    e, s, mask = exact.densest_maximal(n, _edges(g))
+    assert e * sb == eb * s
+    assert np.flatnonzero(mask).tolist() == union
+    assert sum(1 for u, v in _edges(g) if mask[u] and mask[v]) == e and int(mask.sum()) == s
+
+
+def test_maximal_densest_closed_forms():
+    # two equal cliques: both are densest, so is their union
+    e, s, mask = exact.densest_maximal(12, _edges(inputs.disjoint_cliques(6, 6)))
+    assert (e, s) == (30, 12)
+    e, s, mask = exact.densest_maximal(10, _edges(inputs.disjoint_cliques(6, 4)))
+    assert (e, s) == (15, 6) and np.flatnonzero(mask).tolist() == list(range(6))
+    e, s, mask = exact.densest_maximal(7, [])
+    assert (e, s) == (0, 7)
+    g = inputs.star(30)  # k leaves: k / (k + 1) beats every proper subset
+    assert exact.densest_maximal(g.n, _edges(g))[:2] == (29, 30)
+
+
 def _medium_graphs():
     yield inputs.erdos_renyi(400, 2000, 0)
     yield inputs.rmat(9, 8, seed=3)
@@ -270,6 +311,15 @@ def test_guarantee_against_goldberg(gi):
     e_star, s_star, _ = exact.densest_goldberg(g.n, _edges(g))
     for e in EPS:
         _guarantee(_c(g, e), e_star, s_star, e)
+
+
+@pytest.mark.parametrize("gi", range(5))
+def test_maximal_densest_density_equals_goldberg(gi):
+    g = list(_medium_graphs())[gi]
+    e1, s1, _ = exact.densest_goldberg(g.n, _edges(g))
+    e2, s2, mask = exact.densest_maximal(g.n, _edges(g))
+    assert e1 * s2 == e2 * s1
+    assert int(mask.sum()) >= s1  # the largest densest subgraph
 
 
 def test_planted_block_density_is_reached():
