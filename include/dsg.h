@@ -376,6 +376,54 @@ int32_t dsg_batch_run(const dsg_batch_plan* plan, const int32_t* row_ptr, const 
                       void* stream);
 
 /* ------------------------------------------------------------------------
+ * The exact densest subgraph (Section 2: Goldberg's max-flow construction,
+ * the exact method the (2 + 2 eps) guarantee is measured against).
+ *
+ * For a guess rho = p/q, Goldberg's network has a source, a sink and the
+ * graph's vertices; a minimum cut's source side S maximises
+ * q |E(S)| - p |S|.  Dinkelbach's iteration starts from the density of G
+ * and moves to the density of the cut side while that is strictly larger;
+ * at the optimum the largest minimum-cut source side is the largest
+ * densest subgraph S* (the union of every subset of greatest density).
+ * Each maximum flow is a push-relabel preflow on the device.
+ * ------------------------------------------------------------------------ */
+
+/* Result of dsg_exact_density (host struct). */
+typedef struct {
+    int64_t dens_num;  /* |E(S*)| */
+    int64_t dens_den;  /* |S*| (n when the graph has no edge; 0 when n = 0) */
+    int64_t set_size;  /* ids written to set_ids (|S*|, or 0 without set_ids) */
+    int32_t flows;     /* maximum flows solved (Dinkelbach steps) */
+    int32_t relabels;  /* global relabels over all flows */
+} dsg_exact_result;
+
+/* Device workspace bytes of dsg_exact_density for n vertices and m edges:
+ * 12 per adjacency entry (2m of them), 20 per vertex and small tables; 0
+ * for invalid sizes. */
+size_t dsg_exact_workspace_bytes(int64_t n, int64_t m);
+
+/*
+ * The exact maximum density rho* = |E(S*)| / |S*| of g and the largest
+ * densest subgraph S*.
+ *
+ *   g, n, m     CSR as for dsg_peel (device pointers).
+ *   set_ids     device, room for n int32, or NULL: S* in ascending order.
+ *   out         host; filled on DSG_OK.
+ *   workspace   device, >= dsg_exact_workspace_bytes(n, m) bytes, 256-byte
+ *               aligned; NULL makes the library allocate and free it.
+ *   stream      a hipStream_t; the call returns when the result is final
+ *               (it synchronises the stream between the steps of a flow).
+ *
+ * Errors: DSG_EINVAL / DSG_EOVERFLOW for the argument errors of dsg_peel;
+ * DSG_ENOMEM / DSG_EDEVICE for HIP failures; DSG_EINTERNAL if a flow or the
+ * iteration exceeds its step bound or the optimum's cut side is not of the
+ * optimum density (only a CSR outside the contract can cause that).
+ */
+int32_t dsg_exact_density(const dsg_csr* g, int64_t n, int64_t m, int32_t* set_ids,
+                          dsg_exact_result* out, void* workspace, size_t ws_bytes,
+                          void* stream);
+
+/* ------------------------------------------------------------------------
  * Peeling without the host.
  * ------------------------------------------------------------------------ */
 

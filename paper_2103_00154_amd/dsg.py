@@ -27,7 +27,8 @@ DSG_EINTERNAL = -5
 #: every symbol include/dsg.h declares
 EXPORTS = ("dsg_version", "dsg_strerror", "dsg_workspace_bytes", "dsg_peel", "dsg_peel_ex",
            "dsg_validate_csr", "dsg_cbds", "dsg_batch_workspace_bytes", "dsg_batch_prepare",
-           "dsg_batch_run", "dsg_peel_async", "dsg_peel_async_noalloc")
+           "dsg_batch_run", "dsg_peel_async", "dsg_peel_async_noalloc",
+           "dsg_exact_workspace_bytes", "dsg_exact_density")
 
 TRACE_FIELDS = ("s_in", "e_in", "thresh", "removed", "cross", "intra", "walked", "s_out", "e_out")
 
@@ -91,6 +92,11 @@ class BatchPlan(ctypes.Structure):
                 ("ws_bytes", ctypes.c_uint64), ("reserved", _I64 * 4)]
 
 
+class ExactResult(ctypes.Structure):
+    _fields_ = [("dens_num", _I64), ("dens_den", _I64), ("set_size", _I64), ("flows", _I32),
+                ("relabels", _I32)]
+
+
 class DsgError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         text = lib().dsg_strerror(status).decode() if _lib is not None else str(status)
@@ -151,6 +157,11 @@ def lib():
         h.dsg_peel_async_noalloc.argtypes = [ctypes.POINTER(CSR), _I64, _I64, _I64, _I64, _P, _P,
                                              _P, _P, _P]
         h.dsg_peel_async_noalloc.restype = _I32
+        h.dsg_exact_workspace_bytes.argtypes = [_I64, _I64]
+        h.dsg_exact_workspace_bytes.restype = _SZ
+        h.dsg_exact_density.argtypes = [ctypes.POINTER(CSR), _I64, _I64, _P,
+                                        ctypes.POINTER(ExactResult), _P, _SZ, _P]
+        h.dsg_exact_density.restype = _I32
         _lib = h
     return _lib
 
@@ -502,3 +513,48 @@ def peel_async(row_ptr, col_idx, eps=(1, 10), *, workspace, m: int | None = None
 def async_result(res) -> dict:
     """Host dict of a device result written by dsg_peel_async."""
     return Batch.results(res.reshape(1, RESULT_WORDS))[0]
+
+
+# --------------------------------------------------------------------------
+# the exact densest subgraph
+# --------------------------------------------------------------------------
+
+@dataclass
+class Exact:
+    num: int        # |E(S*)|
+    den: int        # |S*|
+    flows: int      # maximum flows solved
+    relabels: int   # global relabels over all flows
+    best: object = None  # torch.int32 device tensor: S* ascending, or None
+
+    @property
+    def density(self) -> float:
+        return self.num / self.den if self.den else 0.0
+
+
+def exact_density(row_ptr, col_idx, *, m: int | None = None, extract: bool = True,
+                  workspace=None, stream=None) -> Exact:
+    """The exact maximum density rho* of the device graph and its largest
+    densest subgraph S* (dsg_exact_density: Goldberg's construction with a
+    device push-relabel flow inside Dinkelbach's iteration)."""
+    import torch
+    _check_int32_cuda("row_ptr", row_ptr)
+    _check_int32_cuda("col_idx", col_idx)
+    n = row_ptr.numel() - 1
+    if m is None:
+        m = col_idx.numel() // 2
+    dev = row_ptr.device
+    best = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if extract else None
+    ws_ptr, ws_len = None, 0
+    if workspace is not None:
+        ws_ptr, ws_len = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    csr = CSR(row_ptr.data_ptr(), col_idx.data_ptr() if col_idx.numel() else None)
+    res = ExactResult()
+    with torch.cuda.device(dev):
+        rc = lib().dsg_exact_density(ctypes.byref(csr), n, m,
+                                     best.data_ptr() if best is not None else None,
+                                     ctypes.byref(res), ws_ptr, ws_len, _stream_handle(stream))
+    if rc != DSG_OK:
+        raise DsgError(rc, "dsg_exact_density")
+    return Exact(num=res.dens_num, den=res.dens_den, flows=res.flows, relabels=res.relabels,
+                 best=best[:res.set_size] if best is not None else None)

@@ -296,3 +296,36 @@ def test_peel_async_noalloc_argument_errors(n, m, num, den, res, status):
     csr = dsg.CSR(0x1000, 0x2000)
     assert h.dsg_peel_async_noalloc(ctypes.byref(csr), n, m, num, den, None, None, res, None,
                                     None) == status
+
+
+# ------------------------------------------------------ exact densest subgraph
+
+def test_exact_struct_and_argument_errors(tmp_path):
+    src = tmp_path / "esizes.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dsg.h"\n'
+                   'int main(void){printf("%zu %zu\\n", sizeof(dsg_exact_result),'
+                   'offsetof(dsg_exact_result, relabels));return 0;}\n')
+    exe = tmp_path / "esizes"
+    subprocess.run(["gcc", "-std=c11", f"-I{ROOT / 'include'}", str(src), "-o", str(exe)],
+                   check=True)
+    got = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True,
+                                       check=True).stdout.split()))
+    assert got == [ctypes.sizeof(dsg.ExactResult), dsg.ExactResult.relabels.offset]
+    h = dsg.lib()
+    csr = dsg.CSR(0x1000, 0x2000)
+    res = dsg.ExactResult()
+    assert h.dsg_exact_density(ctypes.byref(csr), 5, 2, None, None, None, 0, None) == dsg.DSG_EINVAL
+    assert h.dsg_exact_density(ctypes.byref(csr), -1, 2, None, ctypes.byref(res), None, 0,
+                               None) == dsg.DSG_EINVAL
+    assert h.dsg_exact_density(ctypes.byref(csr), 2**31, 2, None, ctypes.byref(res), None, 0,
+                               None) == dsg.DSG_EOVERFLOW
+    assert h.dsg_exact_density(ctypes.byref(csr), 5, 2, None, ctypes.byref(res), 0x10000, 64,
+                               None) == dsg.DSG_EINVAL
+    assert h.dsg_exact_density(ctypes.byref(csr), 0, 0, None, ctypes.byref(res), None, 0,
+                               None) == dsg.DSG_OK
+    assert (res.dens_num, res.dens_den, res.flows) == (0, 0, 0)
+    # 12 bytes per adjacency entry and 20 per vertex, plus small tables
+    n, m = 100_000, 1_000_000
+    ws = h.dsg_exact_workspace_bytes(n, m)
+    assert 24 * m + 20 * n <= ws < 24 * m + 20 * n + 10_000
+    assert h.dsg_exact_workspace_bytes(-1, 0) == 0
