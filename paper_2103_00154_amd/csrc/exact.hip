@@ -21,12 +21,15 @@
 //     (a level-synchronous search from t over reversed residual arcs; N =
 //     n + 2 for vertices that cannot reach t);
 //   * push launches: one wave per active vertex (excess > 0, height < N)
-//     finds its lowest residual neighbour (t counts as height 0), pushes
-//     min(excess, residual) to it if it is lower, else relabels to one
-//     above it.  Residuals and excesses change with device atomics; only a
-//     vertex's own wave lowers its excess and its outgoing residuals, so
-//     concurrent waves never push more than there is (the lock-free scheme
-//     of Hong and He for push-relabel on many threads);
+//     discharges it: to t while that arc has residual, then into every
+//     lower neighbour, 64 arcs per step, each arc taking what the excess
+//     still covers after the arcs before it (a wave prefix sum); excess
+//     left after the whole row relabels the vertex to one above its lowest
+//     remaining residual neighbour.  Residuals and excesses change with
+//     device atomics; only a vertex's own wave lowers its excess and its
+//     outgoing residuals, so concurrent waves never push more than there is
+//     (the lock-free scheme of Hong and He for push-relabel on many
+//     threads);
 //   * global relabels alternate with batches of push launches until no
 //     vertex with excess can reach t.  The preflow is then maximum, and the
 //     vertices that cannot reach t form the largest minimum-cut source side.
@@ -48,7 +51,6 @@ namespace {
 
 constexpr int kExBlock = 256;
 constexpr int kExWaves = kExBlock / 64;
-constexpr int kExOps = 16;          // push / relabel operations per vertex and launch
 constexpr int kExPushLaunches = 8;  // push launches between two global relabels
 constexpr int64_t kExMaxRounds = 20000;  // global relabels per flow (never reached)
 constexpr int kExMaxGuesses = 4096;        // Dinkelbach steps (never reached)
@@ -156,7 +158,12 @@ __global__ __launch_bounds__(kExBlock) void k_ex_active(ExWork w, int64_t n, int
     if (__ballot(act) && lane_id() == 0) w.cnt[0] = 1;
 }
 
-// Push / relabel, one wave per active vertex, up to kExOps operations.
+// Discharge, one wave per active vertex: first to t, then through the row
+// in chunks of 64 arcs.  Every arc into a lower neighbour (admissible) takes
+// what the excess still covers after the admissible arcs before it (a wave
+// prefix sum), so a hub pushes through 64 arcs per step.  If excess is left
+// after the whole row, every admissible arc is saturated and the vertex is
+// relabelled to one above its lowest remaining residual neighbour.
 __global__ __launch_bounds__(kExBlock) void k_ex_push(ExWork w, const int32_t* __restrict__ rp,
                                                       const int32_t* __restrict__ ci, int64_t n,
                                                       int32_t N) {
@@ -165,55 +172,53 @@ __global__ __launch_bounds__(kExBlock) void k_ex_push(ExWork w, const int32_t* _
     for (int64_t u = (int64_t)blockIdx.x * kExWaves + wave_id(); u < n; u += waves) {
         // wave-uniform values are read by lane 0 and broadcast
         int64_t e = __shfl(ld64(w.ex + u), 0, 64);
-        int32_t hu = __shfl(ld32(w.h + u), 0, 64);
+        const int32_t hu = __shfl(ld32(w.h + u), 0, 64);
         if (e <= 0 || hu >= N) continue;  // uniform over the wave
-        const int32_t r0 = rp[u], r1 = rp[u + 1];
-        for (int op = 0; op < kExOps && e > 0 && hu < N; ++op) {
-            // lowest residual neighbour: key = height << 32 | entry
-            unsigned long long key = ~0ull;
-            for (int32_t k = r0 + lane; k < r1; k += 64) {
-                if (ld64(w.res + k) > 0) {
-                    const int32_t x = ci[k];
-                    const unsigned long long hx = (uint32_t)ld32(w.h + x);
-                    key = min(key, (hx << 32) | (uint32_t)k);
-                }
+        const int64_t rt = __shfl(ld64(w.rt + u), 0, 64);
+        if (rt > 0) {
+            // t has height 0, below every vertex
+            const int64_t d = min(e, rt);
+            if (lane == 0) {
+                __hip_atomic_fetch_add(w.rt + u, -d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(w.ex + u, -d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
+            e -= d;
+            if (e == 0) continue;
+        }
+        const int32_t r0 = rp[u], r1 = rp[u + 1];
+        unsigned long long key = ~0ull;  // lowest non-admissible residual arc: h << 32 | entry
+        for (int32_t c0 = r0; c0 < r1 && e > 0; c0 += 64) {
+            const int32_t k = c0 + lane;
+            const int64_t rk = k < r1 ? ld64(w.res + k) : 0;
+            int32_t x = 0, hx = N;
+            if (rk > 0) {
+                x = ci[k];
+                hx = ld32(w.h + x);
+            }
+            const bool adm = rk > 0 && hx < hu;
+            if (rk > 0 && !adm) key = min(key, ((unsigned long long)(uint32_t)hx << 32) | (uint32_t)k);
+            const int64_t amt = adm ? rk : 0;
+            const int64_t incl = wave_incl_sum(amt);
+            const int64_t tot = __shfl(incl, 63, 64);
+            const int64_t before = incl - amt;
+            const int64_t give = adm ? max<int64_t>(0, min(amt, e - before)) : 0;
+            if (give > 0) {
+                __hip_atomic_fetch_add(w.res + k, -give, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(w.res + w.rev[k], give, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(w.ex + x, give, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            const int64_t sent = min(e, tot);
+            if (lane == 0 && sent > 0)
+                __hip_atomic_fetch_add(w.ex + u, -sent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            e -= sent;
+        }
+        if (e > 0) {
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1)
                 key = min(key, (unsigned long long)__shfl_xor(key, off, 64));
-            const int64_t rt = __shfl(ld64(w.rt + u), 0, 64);
-            if (rt > 0) {
-                // t has height 0, below every vertex: push to it
-                const int64_t d = min(e, rt);
-                if (lane == 0) {
-                    __hip_atomic_fetch_add(w.rt + u, -d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_fetch_add(w.ex + u, -d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-                e -= d;
-                continue;
-            }
-            if (key == ~0ull) {  // no residual arc: t is out of reach
-                if (lane == 0) w.h[u] = N;
-                hu = N;
-                break;
-            }
-            const int32_t hmin = (int32_t)(key >> 32);
-            const int32_t k = (int32_t)(key & 0xFFFFFFFFu);
-            if (hu > hmin) {
-                const int64_t d = __shfl(min(e, ld64(w.res + k)), 0, 64);
-                if (lane == 0 && d > 0) {
-                    const int32_t x = ci[k];
-                    __hip_atomic_fetch_add(w.res + k, -d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_fetch_add(w.res + w.rev[k], d, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_fetch_add(w.ex + u, -d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_fetch_add(w.ex + x, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-                e -= d > 0 ? d : 0;
-            } else {
-                hu = min(hmin + 1, N);
-                if (lane == 0) __hip_atomic_store(w.h + u, hu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
+            const int32_t hn = key == ~0ull ? N : min((int32_t)(key >> 32) + 1, N);
+            if (lane == 0) __hip_atomic_store(w.h + u, hn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
