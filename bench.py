@@ -85,6 +85,48 @@ def stored_traffic(workload: str, launches: int):
     return rec.get("bytes_per_launch")
 
 
+def measure_stream(nbytes: int = 4 << 30, reps: int = 5) -> dict:
+    """The hand-written STREAM kernels (measure/stream.hip) on this GPU:
+    copy (b = a) and triad (c = a + 3 b) over int32 arrays of `nbytes`
+    bytes each; median GB/s of bytes read plus written."""
+    import ctypes
+    from paper_2103_00154_amd import _build
+    lib = ctypes.CDLL(str(_build.ensure_stream()))
+    lib.stream_measure.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double)]
+    lib.stream_measure.restype = ctypes.c_int
+    best = None
+    for bpc in (4, 8, 16):
+        c, t = ctypes.c_double(0), ctypes.c_double(0)
+        rc = lib.stream_measure(nbytes, reps, bpc, ctypes.byref(c), ctypes.byref(t))
+        if rc != 0:
+            raise RuntimeError(f"stream_measure failed with HIP error {rc}")
+        log(f"STREAM kernels, {bpc} workgroups per CU: copy {c.value:.0f} GB/s, "
+            f"triad {t.value:.0f} GB/s")
+        if best is None or c.value > best["copy"]:
+            best = {"copy": c.value, "triad": t.value, "blocks_per_cu": bpc}
+    return best
+
+
+def host_cpu() -> dict:
+    """The host's logical CPUs (usable by this process) and CPU model."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"nproc": usable, "cpu_model": model}
+
+
 def measure_copy_gbs(torch, dev, nbytes: int = 4 << 30, reps: int = 5) -> float:
     """Measured copy ceiling of this GPU: a device-to-device copy of `nbytes`
     (hipMemcpyAsync), bytes read plus bytes written per second, median of
@@ -126,7 +168,8 @@ def main() -> int:
                     help="BLOCK,WALK_ITEMS,BLOCKS_PER_CU instead of autotuning")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the serving (Poisson request stream) measurement")
-    ap.add_argument("--serve-qps", type=float, default=2000.0)
+    ap.add_argument("--serve-qps", default="2000,5000,10000,20000",
+                    help="comma list of offered request rates for the load curve")
     ap.add_argument("--serve-requests", type=int, default=3000)
     ap.add_argument("--serve-pool", type=int, default=256)
     ap.add_argument("--serve-streams", type=int, default=4)
@@ -207,6 +250,23 @@ def main() -> int:
     ms_per_step = (t_end - t_start) * 1e3 / args.steps
     gteps = g.m / (ms_per_step * 1e-3) / 1e9
 
+    # the same peel through dsg_peel_async (every pass enqueued up front,
+    # the loop on the device, no host synchronisation): K peels back to back
+    res_async = torch.empty(dsg.RESULT_WORDS, dtype=torch.int64, device=dev)
+    for _ in range(args.warmup):
+        dsg.peel_async(rp, ci, (num, den), workspace=ws, best_ids=best, result=res_async)
+    torch.cuda.synchronize()
+    a_start = time.perf_counter()
+    for _ in range(args.steps):
+        dsg.peel_async(rp, ci, (num, den), workspace=ws, best_ids=best, result=res_async)
+    torch.cuda.synchronize()
+    ms_async = (time.perf_counter() - a_start) * 1e3 / args.steps
+    ra = dsg.async_result(res_async)
+    async_same = (ra["status"], ra["passes"], ra["best_pass"], ra["num"], ra["den"]) == (
+        0, r.passes, r.best_pass, r.num, r.den)
+    log(f"dsg_peel_async: {ms_async:.3f} ms/peel ({g.m / (ms_async * 1e-3) / 1e9:.1f} GTEPS), "
+        f"result {'equal to' if async_same else 'DIFFERENT from'} dsg_peel's")
+
     # the same steps again with HIP events around every launch (on the
     # library's stream) for per-kernel durations
     walk_ms = apply_ms = mark_ms = 0.0
@@ -233,21 +293,27 @@ def main() -> int:
         f"mark {mark_ms / args.steps:.3f} ms")
 
     # neighbour walk (the dominant kernel): algorithmic bytes = 4 B column id
-    # + 4 B neighbour state per walked entry, a 2 B record per degree
-    # decrement, and 12 B per walk-list row (id, prefix offset, row start)
-    walk_bytes = 8 * walked + 2 * cross + 12 * walk_list
+    # + 4 B neighbour state per walked entry (the method's own data); the
+    # design's intermediates - a 2 B record per degree decrement and 12 B per
+    # walk-list row (row start, prefix offset, owner) - are reported apart
+    # as overhead, not counted as algorithmic
+    walk_bytes = 8 * walked
+    overhead = 2 * cross + 12 * walk_list
     per_launch_bytes = walk_bytes / walk_launches
     per_launch_ms = walk_ms / walk_launches
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
     traffic = stored_traffic(args.workload, walk_launches // args.steps)
-    # whole path per step, per unit of work: 8 B per walked entry, 8 B per
-    # degree decrement (record written and read, counter update), 12 B per
-    # live-list test (id, degree, re-write), 12 B per walk-list row and 24 B
-    # per vertex (row_ptr pair, removal pass, extraction read, init writes)
-    path_bytes = (8 * walked + 8 * cross + 12 * live + 12 * walk_list) / args.steps + 24 * g.n
+    # whole path per step, the method's algorithmic bytes: 4 B column id +
+    # 4 B neighbour state per adjacency entry (every row is read once over a
+    # peel: 2m entries), 8 B per degree decrement (read-modify-write of the
+    # counter), 12 B per live-list test (id, degree, re-write) and 24 B per
+    # vertex (row_ptr pair, removal pass, failure list, init degree,
+    # extraction read)
+    path_bytes = 8 * 2 * g.m + (8 * cross + 12 * live) / args.steps + 24 * g.n
     path_gbs = path_bytes / (ms_per_step * 1e-3) / 1e9
     copy_gbs = measure_copy_gbs(torch, dev)
-    log(f"device-to-device copy: {copy_gbs:.0f} GB/s (bytes read + written)")
+    log(f"device-to-device copy (runtime): {copy_gbs:.0f} GB/s (bytes read + written)")
+    stream = measure_stream()
     # the per-pass trace of one more (untimed) peel
     rt = dsg.peel(rp, ci, (num, den), best_ids=best, workspace=ws, trace=True)
     trace_keys = ("s_in", "e_in", "thresh", "removed", "walked", "cross", "intra", "s_out", "e_out")
@@ -268,10 +334,11 @@ def main() -> int:
             o = oracle.peel_graph(g, num, den, trace=True)
             times.append(time.perf_counter() - c0)
         t_cpu = statistics.median(times)
-        cpu = {"value": round(g.m / t_cpu / 1e9, 4), "unit": "GTEPS", "cores": 1,
-               "kind": "oracle",
-               "sample": f"whole workload (n={g.n}, m={g.m}), single-threaded C oracle, "
-                         f"median of {args.cpu_reps} runs, {t_cpu:.2f} s each"}
+        cpu = dict({"value": round(g.m / t_cpu / 1e9, 4), "unit": "GTEPS", "cores": 1,
+                    "kind": "oracle",
+                    "sample": f"whole workload (n={g.n}, m={g.m}), single-threaded C oracle, "
+                              f"median of {args.cpu_reps} runs, {t_cpu:.2f} s each"},
+                   **host_cpu())
         same = ((r.passes, r.best_pass, r.num, r.den) == (o.passes, o.best_pass, o.num, o.den)
                 and bool((best[:r.den].cpu().numpy() == o.best).all()))
         # the per-pass trace too (the thresholds are clamped to int32 on the GPU)
@@ -317,17 +384,26 @@ def main() -> int:
                      "launches_per_step": walk_launches // args.steps,
                      "ms_per_launch": round(per_launch_ms, 4),
                      "alg_bytes_per_launch": int(per_launch_bytes),
-                     "stream_copy": round(copy_gbs, 1),
-                     "frac_of_stream_copy": round(achieved / copy_gbs, 4)},
+                     "alg_bytes_rule": "8 B per walked adjacency entry (column id + neighbour state)",
+                     "overhead_bytes_per_launch": int(overhead / walk_launches),
+                     "stream_copy": round(stream["copy"], 1),
+                     "stream_triad": round(stream["triad"], 1),
+                     "runtime_copy": round(copy_gbs, 1),
+                     "frac_of_stream_copy": round(achieved / stream["copy"], 4)},
         "kernel_ms_per_step": {"instrumented_step": round(ms_profiled, 4),
                                "walk": round(walk_ms / args.steps, 4),
                                "apply": round(apply_ms / args.steps, 4),
                                "mark": round(mark_ms / args.steps, 4)},
         "path_roofline": {"achieved": round(path_gbs, 1), "unit": "GB/s",
                           "frac": round(path_gbs / HBM_PEAK_GBS, 4),
-                          "alg_bytes_per_step": int(path_bytes)},
+                          "alg_bytes_per_step": int(path_bytes),
+                          "alg_bytes_rule": "8 B x 2m + 8 B x sum cross + 12 B x sum |S_in| "
+                                            "+ 24 B x n"},
         "cpu_baseline": cpu,
         "parity": parity,
+        "async": {"entry": "dsg_peel_async", "ms_per_step": round(ms_async, 4),
+                  "gteps": round(g.m / (ms_async * 1e-3) / 1e9, 3),
+                  "same_as_dsg_peel": async_same},
         "pass_trace": pass_trace,
         "batch": batch,
         "serving": serving,
@@ -336,6 +412,7 @@ def main() -> int:
     }
     print(json.dumps(line), flush=True)
     ok = parity in (None, "exact") and (batch is None or batch["parity"] in (None, "exact"))
+    ok = ok and async_same
     ok = ok and (serving is None or serving["parity"] == "exact")
     ok = ok and (eps_sweep is None or eps_sweep["parity"] in (None, "exact"))
     ok = ok and (cbds is None or all(c["parity"] in (None, "exact") for c in cbds["runs"]))
@@ -428,12 +505,27 @@ def bench_batch(args, torch, dsg, num: int, den: int, run_oracle: bool) -> dict:
                 o.passes, o.best_pass, o.num, o.den)
             same = same and bool((h_best[a_i:a_i + len(o.best)] == o.best).all())
         t_cpu = time.perf_counter() - c0
+        # parity over every graph of the batch (the oracle on a thread pool:
+        # each call is one C function that releases the interpreter lock)
+        from concurrent.futures import ThreadPoolExecutor
+
+        def one(i):
+            o = oracle.peel_graph(b.graph(i), num, den, trace=False)
+            r, a_i = got[i], int(b.out_off[i])
+            return ((r["passes"], r["best_pass"], r["num"], r["den"]) == (
+                o.passes, o.best_pass, o.num, o.den)
+                and bool((h_best[a_i:a_i + len(o.best)] == o.best).all()))
+
+        with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as pool:
+            same = same and all(pool.map(one, range(count)))
         parity = "exact" if same else "MISMATCH"
-        cpu = {"value": round(len(sample) / t_cpu, 1), "unit": "graphs/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{len(sample)} graphs (every {count // len(sample)}th, {e_sample} "
-                         f"edges), single-threaded C oracle, {t_cpu:.2f} s"}
-        log(f"batch oracle sample: {len(sample)} graphs in {t_cpu:.2f} s, parity {parity}")
+        cpu = dict({"value": round(len(sample) / t_cpu, 1), "unit": "graphs/s", "cores": 1,
+                    "kind": "oracle",
+                    "sample": f"{len(sample)} graphs (every {count // len(sample)}th, "
+                              f"{e_sample} edges), single-threaded C oracle, {t_cpu:.2f} s"},
+                   **host_cpu())
+        log(f"batch oracle: sample of {len(sample)} graphs in {t_cpu:.2f} s on one core; "
+            f"parity over all {count} graphs {parity}")
     return {
         "workload": (f"{count} graphs, n log-uniform [100, 100000], alternating Erdos-Renyi / "
                      f"Chung-Lu (gamma U[2.1, 2.8]), avg degree U[4, 64], seed 0, "
@@ -452,14 +544,19 @@ def bench_batch(args, torch, dsg, num: int, den: int, run_oracle: bool) -> dict:
         "status_errors": len(bad),
         "cpu_baseline": cpu,
         "parity": parity,
+        "parity_scope": f"all {count} graphs" if parity else None,
     }
 
 
 
 def bench_serve(args, torch) -> dict:
-    """Latency and throughput of the serving loop under a Poisson request
-    stream; every served result is checked against the same graph peeled
-    alone by the single-graph path."""
+    """Latency and throughput of the serving loop under Poisson request
+    streams at rising offered rates (the load curve).  Requests not admitted
+    within 50 ms of arrival are shed, so the served rate saturates instead of
+    collapsing and the served requests keep a bounded latency; the first
+    (lowest) rate is also run without shedding.  Every served result is
+    checked against the same graph and eps peeled alone by the single-graph
+    path."""
     from paper_2103_00154_amd import dsg, inputs, serve
     eps_choices = ((1, 100), (1, 10), (1, 2))
     t0 = time.time()
@@ -470,27 +567,33 @@ def bench_serve(args, torch) -> dict:
     log(f"serve: pool of {len(graphs)} graphs (n median {int(np.median(b.n))}, max "
         f"{int(b.n.max())}; m total {int(b.m.sum())}) built in {time.time() - t0:.1f}s")
     budget = 16 << 30
-    srv = serve.Server(budget, streams=args.serve_streams, max_batch=256)
+    shed_s = 0.05
+    rates = [float(q) for q in args.serve_qps.split(",")]
     # warm-up: a short stream, not timed
-    serve.run_load(srv, hg, eps_choices, qps=args.serve_qps, count=64, seed=99)
-    srv.close()
-    del srv
     srv = serve.Server(budget, streams=args.serve_streams, max_batch=256)
-    reqs = serve.run_load(srv, hg, eps_choices, qps=args.serve_qps, count=args.serve_requests,
-                          seed=7)
-    srv.close()
-    torch.cuda.synchronize()
-    st = serve.latency_stats(reqs)
-    log(f"serve: {st}; {srv.batches} micro-batches (mean {np.mean(srv.batch_sizes):.1f} "
-        f"requests), up to {srv.max_in_flight} in flight, {srv.big_done} requests above "
-        f"{srv.big_vertices} vertices in the single-graph lane ({srv.overflowed} more in "
-        f"batches of their own while the lane was busy), arena peak "
-        f"{srv.arena.peak >> 20} MiB")
+    serve.run_load(srv, hg, eps_choices, qps=rates[0], count=64, seed=99)
+    del srv
+    curve, seen, same = [], {}, True
+    runs = [(rates[0], None)] + [(q, shed_s) for q in rates]
+    for qps, shed in runs:
+        srv = serve.Server(budget, streams=args.serve_streams, max_batch=256, max_queue_s=shed)
+        reqs = serve.run_load(srv, hg, eps_choices, qps=qps, count=args.serve_requests, seed=7)
+        torch.cuda.synchronize()
+        st = serve.latency_stats(reqs)
+        point = dict(st, offered_qps=qps, shed_after_ms=None if shed is None else shed * 1e3,
+                     micro_batches=srv.batches,
+                     mean_batch=round(float(np.mean(srv.batch_sizes)), 2) if srv.batch_sizes
+                     else 0.0,
+                     lane_requests=srv.big_done, arena_peak_bytes=srv.arena.peak)
+        curve.append(point)
+        big_vertices = srv.big_vertices
+        log(f"serve {qps:g} req/s (shed {'off' if shed is None else f'{shed * 1e3:g} ms'}): "
+            f"{st}; {srv.batches} micro-batches, {srv.big_done} large requests in the lane")
+        same = same and all(r.result["status"] == 0 for r in reqs if not r.rejected)
+        for r in reqs:
+            if not r.rejected:
+                seen.setdefault((r.rid % len(graphs), r.eps), []).append(r)
     # every (graph, eps) pair that was served, peeled alone
-    same = all(r.result["status"] == 0 for r in reqs)
-    seen = {}
-    for r in reqs:
-        seen.setdefault((r.rid % len(graphs), r.eps), []).append(r)
     for (gi, e), rs in seen.items():
         g = graphs[gi]
         rp = torch.from_numpy(g.row_ptr).cuda()
@@ -503,35 +606,43 @@ def bench_serve(args, torch) -> dict:
             same = same and np.array_equal(r.best, ab)
     parity = "exact" if same else "MISMATCH"
     log(f"serve: results vs peeled alone: {parity} ({len(seen)} graph/eps pairs)")
-    return dict(st, **{
-        "workload": (f"Poisson stream at {args.serve_qps:g} requests/s of Chung-Lu graphs, n "
-                     f"lognormal (median 20000, sigma 1, capped at 2000000), avg degree U[8, 64], "
-                     f"gamma U[2.1, 2.8], eps from {{1/100, 1/10, 1/2}}; pool of "
-                     f"{len(graphs)} graphs, each request uploads its CSR"),
-        "offered_qps": args.serve_qps, "budget_bytes": budget, "streams": args.serve_streams,
-        "micro_batches": srv.batches, "mean_batch": round(float(np.mean(srv.batch_sizes)), 2),
-        "max_in_flight": srv.max_in_flight, "arena_peak_bytes": srv.arena.peak,
-        "single_graph_lane": {"above_vertices": srv.big_vertices, "requests": srv.big_done,
-                              "overflowed_to_batches": srv.overflowed},
+    head = curve[0]
+    return dict(head, **{
+        "workload": (f"Poisson streams of Chung-Lu graphs, n lognormal (median 20000, sigma 1, "
+                     f"capped at 2000000), avg degree U[8, 64], gamma U[2.1, 2.8], eps from "
+                     f"{{1/100, 1/10, 1/2}}; pool of {len(graphs)} graphs, each request uploads "
+                     f"its CSR; {args.serve_requests} requests per offered rate"),
+        "budget_bytes": budget, "streams": args.serve_streams,
+        "large_request_lane": {"above_vertices": big_vertices, "entry": "dsg_peel_async"},
+        "load_curve": curve,
         "parity": parity})
 
 
 def bench_sweep(args, torch, run_oracle: bool) -> dict:
     """The peel of R-MAT scale 20 at eps from 0 to 5: passes, density, time
-    per eps, each against the oracle (parity and the oracle's time)."""
-    from paper_2103_00154_amd import inputs, sweep
+    per eps and rho(S~) / rho* against the exact densest subgraph computed on
+    the GPU, each against the oracle (parity and the oracle's time)."""
+    from paper_2103_00154_amd import dsg, inputs, sweep
     eps_list = ((0, 1), (1, 100), (1, 20), (1, 10), (1, 2), (1, 1), (2, 1), (5, 1))
     g = inputs.rmat(20, 16, seed=0)
     rp = torch.from_numpy(g.row_ptr).cuda()
     ci = torch.from_numpy(g.col_idx).cuda()
     pts = sweep.eps_sweep(rp, ci, eps_list, reps=5)
+    x0 = time.perf_counter()
+    x = dsg.exact_density(rp, ci, extract=False)
+    x_s = time.perf_counter() - x0
+    log(f"sweep: exact rho* = {x.num}/{x.den} on the GPU in {x_s:.2f} s ({x.flows} flows, "
+        f"{x.relabels} global relabels)")
+    for pt in pts:
+        pt.ratio = pt.num * x.den / (pt.den * x.num)
     rows = []
     same = True
     for pt in pts:
         row = {"eps": f"{pt.eps[0]}/{pt.eps[1]}", "passes": pt.passes, "best_pass": pt.best_pass,
                "dens_num": pt.num, "dens_den": pt.den, "density": round(pt.density, 3),
                "ms": round(pt.ms, 4), "gteps": round(g.m / (pt.ms * 1e-3) / 1e9, 2),
-               "removed_per_pass": [t["removed"] for t in pt.trace]}
+               "removed_per_pass": [t["removed"] for t in pt.trace],
+               "ratio_to_exact": round(pt.ratio, 6)}
         if run_oracle:
             import oracle
             c0 = time.perf_counter()
@@ -543,9 +654,10 @@ def bench_sweep(args, torch, run_oracle: bool) -> dict:
             same = same and ok
         rows.append(row)
         log(f"sweep eps {row['eps']}: passes {pt.passes}, best {pt.num}/{pt.den}, "
-            f"{pt.ms:.3f} ms")
+            f"rho(S~)/rho* {pt.ratio:.4f}, {pt.ms:.3f} ms")
     return {"workload": "R-MAT scale 20, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 0",
             "n": g.n, "m": g.m, "points": rows,
+            "exact_density": [x.num, x.den], "exact_flows": x.flows, "exact_s": round(x_s, 3),
             "parity": ("exact" if same else "MISMATCH") if run_oracle else None,
             "cpu_baseline_kind": "oracle" if run_oracle else None}
 

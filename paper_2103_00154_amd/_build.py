@@ -2,6 +2,8 @@
 
 * ``libdsg.so``       - the HIP peeling library (gfx950) behind ``include/dsg.h``.
 * ``inputs/libgraphgen.so`` - the seeded graph generators (host C, OpenMP).
+* ``measure/libstream.so`` - STREAM copy / triad kernels: the measured HBM
+  ceiling the benchmark reports beside the peak (gfx950).
 
 Both are built in-tree so that the shared objects travel with the source
 tree.  ``build_all()`` always recompiles; ``ensure_built()`` only builds what
@@ -20,6 +22,7 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB_DSG = PKG / "libdsg.so"
 LIB_GEN = PKG / "inputs" / "libgraphgen.so"
+LIB_STREAM = PKG / "measure" / "libstream.so"
 
 HIP_ARCH = "gfx950"
 
@@ -73,15 +76,30 @@ def build_graphgen() -> Path:
     return LIB_GEN
 
 
+def build_stream() -> Path:
+    src = PKG / "measure" / "stream.hip"
+    tmp = LIB_STREAM.with_suffix(".so.tmp")
+    _run([_hipcc(), *HIP_FLAGS, str(src), "-o", str(tmp)])
+    os.replace(tmp, LIB_STREAM)
+    return LIB_STREAM
+
+
 def build_all() -> None:
     build_graphgen()
     build_dsg()
+    build_stream()
 
 
 def ensure_graphgen() -> Path:
     if not LIB_GEN.exists():
         build_graphgen()
     return LIB_GEN
+
+
+def ensure_stream() -> Path:
+    if not LIB_STREAM.exists():
+        build_stream()
+    return LIB_STREAM
 
 
 def ensure_dsg() -> Path:

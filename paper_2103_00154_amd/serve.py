@@ -14,9 +14,16 @@ free their memory, and their results are read back.
 
 Graphs with more vertices than a workgroup keeps in LDS would hold one CU
 for a long time (their state spills to device memory), so they take a
-separate lane instead: worker threads peel them one at a time with the
-multi-kernel single-graph path (dsg_peel_ex), which spreads one graph over
-the whole device, on streams of their own, concurrently with the batches.
+separate lane instead: each is peeled by the single-graph path without the
+host (dsg_peel_async: every pass enqueued at once, the pass loop on the
+device), which spreads one graph over the whole device, on one of several
+lane streams, concurrently with the batches.  The serving thread enqueues a
+large request and moves on; an event tells when its result has arrived.
+
+Under a load beyond capacity the server can shed work: with ``max_queue_s``
+set, a request still waiting that long after its arrival is rejected
+(``Request.rejected``) instead of being admitted, so the requests that are
+served keep a bounded latency and the served rate stays at capacity.
 
 Every result is exactly the result of peeling the graph alone: the kernels
 are exact integer code, and in a batch a graph is peeled by one workgroup,
@@ -25,7 +32,6 @@ independently of what else shares the launch.
 from __future__ import annotations
 
 import bisect
-import threading
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -105,6 +111,17 @@ class Request:
     done: float = -1.0
     result: dict | None = None
     best: np.ndarray | None = None
+    rejected: bool = False
+
+
+@dataclass
+class _LaneJob:
+    req: Request
+    stream: object
+    event: object
+    allocs: list                  # (offset, bytes) in the arena
+    res_host: object              # pinned copy of the device result
+    best_host: object             # pinned copy of the best-id slots
 
 
 @dataclass
@@ -134,27 +151,29 @@ class Server:
 
     ``big_vertices``: requests with more vertices go to the single-graph lane
     (None: the LDS vertex capacity of the batch kernel's launch shape; 0 or a
-    huge value disables the lane); ``big_lanes`` worker threads serve it.
+    huge value disables the lane); ``big_lanes`` lane streams carry them.
     ``reserve_cus``: CUs kept free of batch workgroups for the single-graph
     lane (None: a quarter of the CUs while the lane is on).  A persistent
     batch workgroup holds most of its CU's LDS, so without a reserve a loaded
     server leaves the lane's kernels no CU to run on; each micro-batch's grid
     is capped at (CUs - reserve) / streams workgroups.
     ``overflow``: when the lane has a backlog (twice as many requests waiting
-    as it has workers), a large request goes to the batch kernel instead, in
-    a micro-batch of its own (so that its long run on one CU delays no other
-    request's result)."""
+    as it has streams), a large request goes to the batch kernel instead, in
+    a micro-batch of its own.
+    ``max_queue_s``: shed load - a request not admitted within this many
+    seconds of its arrival is rejected (None: every request waits its turn).
+    """
 
     def __init__(self, budget_bytes: int, *, streams: int = 4, max_batch: int = 512,
                  launch: dict | None = None, device=None, big_vertices: int | None = None,
-                 big_lanes: int = 2, reserve_cus: int | None = None, overflow: bool = True):
+                 big_lanes: int = 4, reserve_cus: int | None = None, overflow: bool = False,
+                 max_queue_s: float | None = None):
         import torch
         self.device = torch.device(device or "cuda")
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.buf = torch.empty(budget_bytes, dtype=torch.uint8, device=self.device)
         self.arena = Arena(budget_bytes)
-        self.lock = threading.Lock()
         if big_vertices is None:
             big_vertices = _lds_vertices(launch, self.device)
         self.big_vertices = big_vertices
@@ -163,22 +182,19 @@ class Server:
             reserve_cus = cus // 4 if big_vertices else 0
         self.batch_grid = max(1, (cus - min(reserve_cus, cus - 1)) // max(streams, 1))
         self.big_waiting: deque[Request] = deque()
-        self.big_busy = 0
         self.big_done = 0
-        self._stop = False
         self.error: BaseException | None = None
-        self._cv = threading.Condition(self.lock)
-        self._lanes = []
-        for _ in range(big_lanes if big_vertices else 0):
-            th = threading.Thread(target=self._big_lane, daemon=True)
-            th.start()
-            self._lanes.append(th)
+        nl = big_lanes if big_vertices else 0
+        self.lane_streams = [torch.cuda.Stream(device=self.device) for _ in range(nl)]
+        self.lane_busy: list = [None] * nl
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self.busy = [None] * streams
         self.waiting: deque[Request] = deque()
         self.solo: deque[Request] = deque()   # large requests overflowing into batches
         self.overflow = overflow
         self.overflowed = 0
+        self.max_queue_s = max_queue_s
+        self.rejected = 0
         self.max_batch = max_batch
         self.launch = launch
         self.completed: list[Request] = []
@@ -197,94 +213,24 @@ class Server:
         if need > self.arena.size:
             raise ValueError(f"request {req.rid} needs more memory than the whole budget")
         if big:
-            with self._cv:
-                backlog = len(self.big_waiting) >= 2 * len(self._lanes)
-                if not (self.overflow and backlog and
-                        footprint(req.graph.n, req.graph.m) <= self.arena.size):
-                    self.big_waiting.append(req)
-                    self._cv.notify()
-                    return
-            self.solo.append(req)
-            self.overflowed += 1
+            backlog = len(self.big_waiting) >= 2 * max(len(self.lane_streams), 1)
+            if (self.overflow and backlog and
+                    footprint(req.graph.n, req.graph.m) <= self.arena.size):
+                self.solo.append(req)
+                self.overflowed += 1
+            else:
+                self.big_waiting.append(req)
         else:
             self.waiting.append(req)
 
     @property
     def idle(self) -> bool:
-        with self.lock:
-            big_idle = not self.big_waiting and self.big_busy == 0
-        return (big_idle and not self.waiting and not self.solo
-                and all(b is None for b in self.busy))
+        return (not self.big_waiting and not self.waiting and not self.solo
+                and all(b is None for b in self.busy)
+                and all(j is None for j in self.lane_busy))
 
     def close(self) -> None:
-        with self._cv:
-            self._stop = True
-            self._cv.notify_all()
-        for th in self._lanes:
-            th.join()
-
-    def _big_lane(self) -> None:
-        try:
-            self._big_lane_loop()
-        except BaseException as exc:  # surfaced by tick() in the serving thread
-            with self._cv:
-                self.error = exc
-
-    def _big_lane_loop(self) -> None:
-        """Worker: peel large requests one at a time with the single-graph
-        path, each with its own arena region, on a stream of its own."""
-        import torch
-        torch.cuda.set_device(self.device)
-        stream = torch.cuda.Stream(device=self.device)
-        while True:
-            with self._cv:
-                while not self._stop and not self.big_waiting:
-                    self._cv.wait()
-                if self._stop:
-                    return
-                rq = self.big_waiting[0]
-                g = rq.graph
-                nb_csr = 4 * (g.n + 1 + 2 * g.m)
-                nb_ws = dsg.workspace_bytes(g.n, g.m)
-                got = self._try_place((nb_csr, 4 * max(g.n, 1), nb_ws))
-                if got is None:
-                    self._cv.wait(0.0005)   # memory frees up as batches finish
-                    continue
-                self.big_waiting.popleft()
-                self.big_busy += 1
-            rq.admitted = self.now()
-            (o_csr, _), (o_best, _), (o_ws, _) = got
-            ints = self.buf.view(torch.int32)
-            try:
-                with torch.cuda.stream(stream):
-                    dev = ints[o_csr // 4:o_csr // 4 + g.csr.numel()]
-                    dev.copy_(g.csr, non_blocking=True)
-                    best = ints[o_best // 4:o_best // 4 + max(g.n, 1)]
-                    # passes in batches of eight with one host check each:
-                    # next to the batch launches of other threads, waiting
-                    # on the device before every pass (the default) exposes
-                    # each pass's launches to the contended runtime
-                    r = dsg.peel(dev[:g.n + 1], dev[g.n + 1:] if g.m else dev[:1], rq.eps,
-                                 m=g.m, best_ids=best, workspace=self.buf[o_ws:o_ws + nb_ws],
-                                 launch={"pass_batch": 8}, stream=stream)
-                    b = r.best.cpu().numpy()
-                rq.result = {"num": r.num, "den": r.den, "passes": r.passes,
-                             "best_pass": r.best_pass, "best_size": len(b), "status": 0}
-                rq.best = b
-            except BaseException as exc:  # surfaced by tick() in the serving thread
-                status = exc.status if isinstance(exc, dsg.DsgError) else dsg.DSG_EINTERNAL
-                rq.result = {"num": 0, "den": 0, "passes": 0, "best_pass": 0, "best_size": 0,
-                             "status": status}
-                rq.best = np.zeros(0, dtype=np.int32)
-                with self._cv:
-                    self.error = exc
-            rq.done = self.now()
-            with self._cv:
-                for off, nb in got:
-                    self.arena.free(off, nb)
-                self.completed.append(rq)
-                self.big_busy -= 1
-                self.big_done += 1
+        """Nothing runs in the background; kept for callers that close."""
 
     # ------------------------------------------------------------------
     def _reap(self) -> None:
@@ -299,11 +245,35 @@ class Server:
                 rq.result = results[i]
                 a = mb.best_off[i]
                 rq.best = best[a:a + rq.result["best_size"]].copy()
-            with self.lock:
-                for off, nb in mb.allocs:
-                    self.arena.free(off, nb)
-                self.completed.extend(mb.reqs)
+            for off, nb in mb.allocs:
+                self.arena.free(off, nb)
+            self.completed.extend(mb.reqs)
             self.busy[k] = None
+        for k, job in enumerate(self.lane_busy):
+            if job is None or not job.event.query():
+                continue
+            rq = job.req
+            rq.done = self.now()
+            rq.result = dsg.Batch.results(job.res_host)[0]
+            rq.best = job.best_host.numpy()[:rq.result["best_size"]].copy()
+            for off, nb in job.allocs:
+                self.arena.free(off, nb)
+            self.completed.append(rq)
+            self.big_done += 1
+            self.lane_busy[k] = None
+
+    def _shed(self) -> None:
+        """Reject the requests that have waited longer than max_queue_s."""
+        if self.max_queue_s is None:
+            return
+        now = self.now()
+        for q in (self.waiting, self.big_waiting, self.solo):
+            while q and now - q[0].arrival > self.max_queue_s:
+                rq = q.popleft()
+                rq.rejected = True
+                rq.done = now
+                self.rejected += 1
+                self.completed.append(rq)
 
     def _shared_bytes(self, take) -> tuple[int, int]:
         sum_n = sum(r.graph.n for r in take)
@@ -321,11 +291,42 @@ class Server:
             got.append((off, nb))
         return got
 
-    def _launch(self, k: int, queue=None) -> None:
-        with self.lock:
-            self._launch_locked(k, self.waiting if queue is None else queue,
-                                self.max_batch if queue is None else 1)
+    def _launch_lane(self, k: int) -> bool:
+        """Enqueue the head large request on lane stream k (upload, device
+        peel, result copies, event); False if its memory is not free yet."""
+        import torch
+        rq = self.big_waiting[0]
+        g = rq.graph
+        nb_csr = 4 * (g.n + 1 + 2 * g.m)
+        nb_ws = dsg.workspace_bytes(g.n, g.m)
+        got = self._try_place((nb_csr, 4 * max(g.n, 1), nb_ws))
+        if got is None:
+            return False
+        self.big_waiting.popleft()
+        rq.admitted = self.now()
+        (o_csr, _), (o_best, _), (o_ws, _) = got
+        ints = self.buf.view(torch.int32)
+        s = self.lane_streams[k]
+        with torch.cuda.stream(s):
+            dev = ints[o_csr // 4:o_csr // 4 + g.csr.numel()]
+            dev.copy_(g.csr, non_blocking=True)
+            best = ints[o_best // 4:o_best // 4 + max(g.n, 1)]
+            res = torch.empty(dsg.RESULT_WORDS, dtype=torch.int64, device=self.device)
+            dsg.peel_async(dev[:g.n + 1], dev[g.n + 1:] if g.m else dev[:1], rq.eps, m=g.m,
+                           workspace=self.buf[o_ws:o_ws + nb_ws], best_ids=best, result=res,
+                           stream=s)
+            res_host = torch.empty(dsg.RESULT_WORDS, dtype=torch.int64, pin_memory=True)
+            res_host.copy_(res, non_blocking=True)
+            best_host = torch.empty(best.numel(), dtype=torch.int32, pin_memory=True)
+            best_host.copy_(best, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        self.lane_busy[k] = _LaneJob(rq, s, ev, got, res_host.view(1, -1), best_host)
+        return True
 
+    def _launch(self, k: int, queue=None) -> None:
+        self._launch_locked(k, self.waiting if queue is None else queue,
+                            self.max_batch if queue is None else 1)
     def _launch_locked(self, k: int, queue, max_batch: int) -> None:
         import torch
         take, allocs = [], []
@@ -391,10 +392,15 @@ class Server:
         self.max_in_flight = max(self.max_in_flight, sum(b is not None for b in self.busy))
 
     def tick(self) -> None:
-        """Reap finished micro-batches, then launch new ones on free streams."""
-        if self.error is not None:
-            raise RuntimeError("single-graph lane failed") from self.error
+        """Reap finished work, shed requests waiting too long, then launch
+        large requests on free lane streams and micro-batches on free batch
+        streams."""
         self._reap()
+        self._shed()
+        for k in range(len(self.lane_busy)):
+            if self.lane_busy[k] is None and self.big_waiting:
+                if not self._launch_lane(k):
+                    break
         # overflowing large requests use at most half of the streams
         solo_cap = max(1, len(self.busy) // 2)
         for k in range(len(self.busy)):
@@ -467,11 +473,17 @@ def run_load(server: Server, graphs: list, eps_choices, qps: float, count: int,
 
 
 def latency_stats(reqs: list[Request]) -> dict:
-    lat = np.array([r.done - r.arrival for r in reqs]) * 1e3
-    queue = np.array([r.admitted - r.arrival for r in reqs]) * 1e3
+    """Latency of the served requests (arrival to host-visible result), the
+    rate they were served at over the run, and how many were rejected."""
+    served = [r for r in reqs if not r.rejected]
     span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
-    return {"requests": len(reqs), "p50_ms": round(float(np.percentile(lat, 50)), 3),
-            "p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "mean_ms": round(float(lat.mean()), 3),
-            "queue_p50_ms": round(float(np.percentile(queue, 50)), 3),
-            "graphs_per_s": round(len(reqs) / span, 1)}
+    out = {"requests": len(reqs), "served": len(served), "rejected": len(reqs) - len(served),
+           "graphs_per_s": round(len(served) / span, 1)}
+    if served:
+        lat = np.array([r.done - r.arrival for r in served]) * 1e3
+        queue = np.array([r.admitted - r.arrival for r in served]) * 1e3
+        out.update({"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                    "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                    "mean_ms": round(float(lat.mean()), 3),
+                    "queue_p50_ms": round(float(np.percentile(queue, 50)), 3)})
+    return out

@@ -111,13 +111,13 @@ def test_large_requests_overflow_into_batches_when_the_lane_is_backed_up():
     import torch
     from paper_2103_00154_amd import serve
     # only graphs larger than the LDS vertex state, all arriving at once, one
-    # lane worker: the lane's queue backs up and later requests overflow into
-    # micro-batches of their own on the batch kernel
+    # lane stream and overflow on: the lane's queue backs up and later
+    # requests overflow into micro-batches of their own on the batch kernel
     graphs = [inputs.chung_lu(150_000, 16, 2.3, seed=81), inputs.erdos_renyi(100_000, 300_000, 82),
               inputs.chung_lu(120_000, 24, 2.6, seed=83)]
     alone = _alone(graphs)
     hg = [serve.HostGraph.from_graph(g) for g in graphs]
-    srv = serve.Server(4 << 30, streams=4, max_batch=8, big_lanes=1)
+    srv = serve.Server(4 << 30, streams=4, max_batch=8, big_lanes=1, overflow=True)
     assert all(g.n > srv.big_vertices for g in graphs)
     reqs = serve.run_load(srv, hg, EPS, qps=1e6, count=24, seed=6)
     srv.close()
@@ -127,3 +127,25 @@ def test_large_requests_overflow_into_batches_when_the_lane_is_backed_up():
     assert srv.overflowed + srv.big_done == 24
     assert srv.arena.used == 0
     _check(reqs, graphs, alone)
+
+
+def test_load_beyond_capacity_is_shed_and_served_results_stay_exact():
+    import torch
+    from paper_2103_00154_amd import serve
+    # far more requests per second than the device serves: requests that
+    # wait more than 20 ms are rejected; the rest keep a bounded latency and
+    # their results are exact
+    graphs = _pool(32, seed=9, median=20_000, cap=400_000)
+    alone = _alone(graphs)
+    hg = [serve.HostGraph.from_graph(g) for g in graphs]
+    srv = serve.Server(8 << 30, streams=4, max_batch=64, max_queue_s=0.02)
+    reqs = serve.run_load(srv, hg, EPS, qps=200_000, count=2000, seed=10)
+    torch.cuda.synchronize()
+    st = serve.latency_stats(reqs)
+    say(f"stats {st}; lane {srv.big_done}, rejected {srv.rejected}")
+    assert st["rejected"] > 0 and st["served"] > 0
+    assert st["served"] + st["rejected"] == 2000 and srv.arena.used == 0
+    served = [r for r in reqs if not r.rejected]
+    # admitted within the shedding bound (checked at every tick)
+    assert max(r.admitted - r.arrival for r in served) < 0.02 + 0.05
+    _check(served, graphs, alone)

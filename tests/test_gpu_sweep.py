@@ -44,8 +44,10 @@ def test_sweep_meets_the_guarantee_against_the_exact_densest(gi):
          inputs.rmat(11, 16, seed=7, planted=(40, 0.6, 8))][gi]
     e_star, s_star, _ = exact.densest_goldberg(g.n, g.edges())
     rp, ci = to_device(g)
-    for pt in sweep.eps_sweep(rp, ci, EPS, reps=1):
+    for pt in sweep.eps_sweep(rp, ci, EPS, reps=1, exact=True):
         num, den = pt.eps
+        # the ratio the sweep reports from the GPU's rho* is the oracle's
+        assert abs(pt.ratio - pt.num * s_star / (pt.den * e_star)) < 1e-12
         # rho(S~) >= rho* / (2 + 2 eps), in integers
         assert 2 * (num + den) * pt.num * s_star >= den * e_star * pt.den, pt.eps
         say(f"{g.name} eps {num}/{den}: rho(S~) / rho* = "
