@@ -11,7 +11,7 @@ constexpr int kBlock = 256;                      // threads per workgroup (4 wav
 constexpr int kWaves = kBlock / 64;
 constexpr int kMarkItems = 8;                    // live-list entries per thread
 constexpr int kMarkTile = kBlock * kMarkItems;   // live-list entries per tile
-constexpr int kWalkItems = 16;                   // adjacency entries per thread
+constexpr int kWalkItems = 8;                    // adjacency entries per thread
 constexpr int kWalkTile = kBlock * kWalkItems;   // adjacency entries per tile
 constexpr int kFewRows = 4;                      // tiles over <= this many rows skip the owner table
 constexpr int kMaxWalkGrid = 4096;               // walk workgroups (one partial count each)
@@ -30,7 +30,7 @@ constexpr int kNbLds = 1024;                     // bins the walk can stage in L
 constexpr int kScanBlock = 256;                  // threads of the tile-scan workgroup
 constexpr int kApplyBlock = 1024;                // threads of an apply workgroup
 constexpr int kApplyBatch = 16;                  // record loads per lane before counting
-constexpr int kApplyTiles = 2048;                // tiles whose run bounds k_apply stages in LDS
+constexpr int kApplyTiles = 4096;                // tiles whose run bounds k_apply stages in LDS
 constexpr int64_t kChunkMin = 8192;              // least records per apply work item
 constexpr int64_t kTargetItems = 512;            // apply work items aimed for per pass
 

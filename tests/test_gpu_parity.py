@@ -160,7 +160,7 @@ def test_walk_grid_above_partial_slots(dsg):
 @pytest.mark.parametrize("shape", ["matching", "stars", "paths"])
 def test_walk_tiles_over_thousands_of_rows(dsg, shape):
     # a 60-clique survives the first pass while thousands of pendant rows of
-    # length 1 fail: one 4096-entry walk tile spans up to 4096 rows, so the
+    # length 1 fail: one 2048-entry walk tile spans up to 2048 rows, so the
     # row table takes several rounds and the owner scan covers every entry
     k = 60
     extra = {"matching": (20_000, [(2 * i, 2 * i + 1) for i in range(10_000)]),
