@@ -109,6 +109,32 @@ def measure_stream(nbytes: int = 4 << 30, reps: int = 5) -> dict:
     return best
 
 
+def measure_gather(n_ids: int, lookups: int = 1 << 27, reps: int = 5) -> dict:
+    """The walk's lookup ceiling on this GPU (measure/stream.hip): uniformly
+    random ids below the next power of two of `n_ids`, each read once and
+    used for one 8-byte gather from a table of one word per 32 ids (the
+    rank directory's shape); median billions of lookups per second."""
+    import ctypes
+    from paper_2103_00154_amd import _build
+    lib = ctypes.CDLL(str(_build.ensure_stream()))
+    lib.gather_measure.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_double)]
+    lib.gather_measure.restype = ctypes.c_int
+    lg = min(30, max(5, (max(n_ids, 2) - 1).bit_length()))
+    best = None
+    for bpc in (4, 8):
+        v = ctypes.c_double(0)
+        rc = lib.gather_measure(lookups, lg, reps, bpc, ctypes.byref(v))
+        if rc != 0:
+            raise RuntimeError(f"gather_measure failed with HIP error {rc}")
+        log(f"gather probe, {bpc} workgroups per CU: {v.value:.1f} G lookups/s "
+            f"({lookups} random ids below 2^{lg}, table {(1 << lg) // 32 * 8} B)")
+        if best is None or v.value > best["glookups_per_s"]:
+            best = {"glookups_per_s": round(v.value, 1), "lookups": lookups, "ids": 1 << lg,
+                    "table_bytes": (1 << lg) // 32 * 8, "blocks_per_cu": bpc}
+    return best
+
+
 def host_cpu() -> dict:
     """The host's logical CPUs (usable by this process) and CPU model."""
     model = "unknown"
@@ -314,6 +340,7 @@ def main() -> int:
     copy_gbs = measure_copy_gbs(torch, dev)
     log(f"device-to-device copy (runtime): {copy_gbs:.0f} GB/s (bytes read + written)")
     stream = measure_stream()
+    gather = measure_gather(g.n)
     # the per-pass trace of one more (untimed) peel
     rt = dsg.peel(rp, ci, (num, den), best_ids=best, workspace=ws, trace=True)
     trace_keys = ("s_in", "e_in", "thresh", "removed", "walked", "cross", "intra", "s_out", "e_out")
@@ -389,7 +416,9 @@ def main() -> int:
                      "stream_copy": round(stream["copy"], 1),
                      "stream_triad": round(stream["triad"], 1),
                      "runtime_copy": round(copy_gbs, 1),
-                     "frac_of_stream_copy": round(achieved / stream["copy"], 4)},
+                     "frac_of_stream_copy": round(achieved / stream["copy"], 4),
+                     "walk_gentries_per_s": round(walked / (walk_ms * 1e-3) / 1e9, 1),
+                     "gather_ceiling": gather},
         "kernel_ms_per_step": {"instrumented_step": round(ms_profiled, 4),
                                "walk": round(walk_ms / args.steps, 4),
                                "apply": round(apply_ms / args.steps, 4),

@@ -137,7 +137,7 @@ const char* dsg_strerror(int32_t status);
 
 /* Bytes of device workspace dsg_peel needs for a graph with n vertices and
  * m undirected edges; 0 for invalid sizes.  About 28 n + 4 m bytes, plus
- * 2 * (ceil(2m / 4096) + 1) * (min(ceil(n / 32768) + 1, 1024) + 1) bytes of
+ * 2 * (ceil(2m / 2048) + 1) * (min(ceil(n / 32768) + 1, 1024) + 1) bytes of
  * per-tile bin offsets, min(n, 32768) * 4 bytes per degree-update work item
  * (at most n / 32768 + 514 items) and about 40 KB of fixed tables. */
 size_t dsg_workspace_bytes(int64_t n, int64_t m);
