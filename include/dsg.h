@@ -317,7 +317,10 @@ typedef struct {
     int32_t walk_items;
     int32_t lds_bytes;    /* dynamic LDS per workgroup (vertex states) */
     int32_t lds_vertices; /* vertices per graph whose state lives in LDS */
-    int32_t reserved0;
+    int32_t state_bits;   /* 16, or 8 when the batch's largest graph has more
+                             vertices than 16-bit states fit in the LDS
+                             (degrees of 240 and more then sit in an LDS
+                             hash table) */
     int64_t out_len;      /* slots of best_ids / removed_at */
     void* workspace;
     uint64_t ws_bytes;

@@ -29,6 +29,15 @@
 // half-word).  Vertex ids at or above `cap` (graphs larger than the LDS),
 // and large degrees beyond the table, use device memory and device atomics.
 //
+// Batches whose largest graph has more vertices than the LDS holds 16-bit
+// states use 8-bit states instead (the plan's state_bits): the degree
+// itself while below 0xF0, a marker for "degree in the LDS hash table"
+// (keyed by vertex id, linear probing, for the few vertices of larger
+// degree), "failed in this pass", "failed earlier" and "degree kept in
+// device memory" (a hash table too full to take it).  A decrement of a
+// degree held in the state is an LDS atomic on its byte of the 32-bit
+// word, as for 16-bit states.
+//
 // All arithmetic is exact integer arithmetic, so results equal those of
 // dsg_peel and of a sequential peel for every launch shape.
 
@@ -53,6 +62,14 @@ constexpr uint32_t kStNow = 0xFFFEu;     // failed in the current pass
 constexpr uint32_t kStGlobal = 0xFFFDu;  // present, degree in device memory
 constexpr uint32_t kStSlot0 = 0xFE00u;   // present, degree in big-degree slot s - kStSlot0
 constexpr int kSlots = (int)(kStGlobal - kStSlot0);
+// 8-bit vertex states
+constexpr uint32_t kS8Dead = 0xFFu;      // failed in an earlier pass
+constexpr uint32_t kS8Now = 0xFEu;       // failed in the current pass
+constexpr uint32_t kS8Global = 0xFDu;    // present, degree in device memory
+constexpr uint32_t kS8Hash = 0xF0u;      // present, degree in the LDS hash table
+constexpr int kHashBits = 12;
+constexpr int kHashSlots = 1 << kHashBits;  // (key, degree) pairs: 32 KB of LDS
+constexpr int kHashProbes = 64;          // probes before a degree goes to device memory
 constexpr int kBMarkItems = 4;           // live-list entries per thread per mark chunk
 constexpr int kMinWaveTile = 64 * 4;     // smallest wave tile (sizes the tile table)
 constexpr int32_t kNoStart = INT32_MIN;  // no row starts at this entry (row bases are larger)
@@ -71,6 +88,7 @@ struct alignas(256) BHead {
 };
 
 struct BWork {
+    int32_t state_bits;  // 16 or 8 (the kernel instantiation this work is for)
     const BGraph* gs;
     BHead* head;
     int32_t* gdeg;  // degrees kept in device memory (ids >= cap, overflow)
@@ -103,25 +121,49 @@ __device__ inline void dec_global(int32_t* p) {
     __hip_atomic_fetch_sub(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ inline uint32_t hash_home(int32_t v) {
+    return ((uint32_t)v * 0x9E3779B1u) >> (32 - kHashBits);  // Fibonacci hashing
+}
+
+// Slot of a vertex whose 8-bit state says its degree is in the hash table
+// (inserted within kHashProbes probes of its home slot).
+__device__ inline int32_t hash_find(const int32_t* keys, int32_t v) {
+    uint32_t h = hash_home(v);
+    for (int p = 0; p < kHashProbes; ++p) {
+        if (keys[h] == v) return (int32_t)h;
+        h = (h + 1) & (kHashSlots - 1);
+    }
+    return 0;  // cannot happen: the state is set only after a successful insert
+}
+
 // Degree of a vertex still present.
-__device__ inline int32_t live_degree(int32_t v, int32_t cap, const uint16_t* st16,
-                                      const int32_t* big, const int32_t* gdeg) {
+template <int SW>
+__device__ inline int32_t live_degree(int32_t v, int32_t cap, const uint32_t* s_state,
+                                      const int32_t* big, const int32_t* hkey,
+                                      const int32_t* hval, const int32_t* gdeg) {
     if (v < cap) {
-        const uint32_t s = st16[v];
-        if (s < kStSlot0) return (int32_t)s;
-        if (s < kStGlobal) return big[s - kStSlot0];
+        if constexpr (SW == 16) {
+            const uint32_t s = reinterpret_cast<const uint16_t*>(s_state)[v];
+            if (s < kStSlot0) return (int32_t)s;
+            if (s < kStGlobal) return big[s - kStSlot0];
+        } else {
+            const uint32_t s = reinterpret_cast<const uint8_t*>(s_state)[v];
+            if (s < kS8Hash) return (int32_t)s;
+            if (s == kS8Hash) return hval[hash_find(hkey, v)];
+        }
     }
     return load_coherent(gdeg + v);
 }
 
-template <int NT, int IT>
+template <int NT, int IT, int SW>
 __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __restrict__ rp_all,
                                                    const int32_t* __restrict__ ci_all) {
+    static_assert(SW == 16 || SW == 8, "16- or 8-bit vertex states");
     constexpr int NW = NT / 64;
     constexpr int WT = 64 * IT;          // wave tile
     constexpr int CH = NT * kBMarkItems;  // mark chunk
     static_assert(IT % 4 == 0, "owner rows move as int4");
-    extern __shared__ uint32_t s_state[];  // two 16-bit vertex states per word
+    extern __shared__ uint32_t s_state[];  // two 16-bit or four 8-bit vertex states per word
     __shared__ __align__(16) int32_t s_own[NW * WT];
     __shared__ int32_t s_big[kSlots];
     __shared__ unsigned long long s_red64[NW];
@@ -129,6 +171,10 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
     __shared__ int32_t s_q, s_nslots;
 
     uint16_t* st16 = reinterpret_cast<uint16_t*>(s_state);
+    uint8_t* st8 = reinterpret_cast<uint8_t*>(s_state);
+    // 8-bit states: the hash table follows the states (w.cap is a multiple of 16)
+    int32_t* s_hkey = reinterpret_cast<int32_t*>(s_state) + (w.cap >> 2);
+    int32_t* s_hval = s_hkey + kHashSlots;
     const int tid = threadIdx.x;
     const int lane = lane_id();
     const int wid = wave_id();
@@ -162,6 +208,8 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
         // is checked by the first mark, chunk by chunk, before any use
         if (n > 0 && (rp[0] != 0 || rp[n] != m2)) status = DSG_EINVAL;
         if (tid == 0) s_nslots = 0;
+        if constexpr (SW == 8)
+            for (int i = tid; i < kHashSlots; i += NT) s_hkey[i] = -1;
         __syncthreads();
 
         while (status == DSG_OK && S > 0) {
@@ -209,7 +257,9 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
 #pragma unroll
                     for (int j = 0; j < kBMarkItems; ++j) {
                         if (i0 + j >= nlive) v[j] = -1;
-                        d[j] = v[j] >= 0 ? live_degree(v[j], cap, st16, s_big, gdeg) : 0;
+                        d[j] = v[j] >= 0 ? live_degree<SW>(v[j], cap, s_state, s_big, s_hkey,
+                                                           s_hval, gdeg)
+                                         : 0;
                     }
                     int32_t re[kBMarkItems];
 #pragma unroll
@@ -256,17 +306,37 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
                             const int32_t dx = d[j];
                             bool in_lds = false;
                             if (x < cap) {
-                                if (dx < (int32_t)kStSlot0) {
-                                    st16[x] = (uint16_t)dx;
-                                    in_lds = true;
-                                } else {
-                                    const int32_t s = atomicAdd(&s_nslots, 1);
-                                    if (s < kSlots) {
-                                        s_big[s] = dx;
-                                        st16[x] = (uint16_t)(kStSlot0 + s);
+                                if constexpr (SW == 16) {
+                                    if (dx < (int32_t)kStSlot0) {
+                                        st16[x] = (uint16_t)dx;
                                         in_lds = true;
                                     } else {
-                                        st16[x] = (uint16_t)kStGlobal;
+                                        const int32_t s = atomicAdd(&s_nslots, 1);
+                                        if (s < kSlots) {
+                                            s_big[s] = dx;
+                                            st16[x] = (uint16_t)(kStSlot0 + s);
+                                            in_lds = true;
+                                        } else {
+                                            st16[x] = (uint16_t)kStGlobal;
+                                        }
+                                    }
+                                } else {
+                                    if (dx < (int32_t)kS8Hash) {
+                                        st8[x] = (uint8_t)dx;
+                                        in_lds = true;
+                                    } else {
+                                        // linear probing from the home slot
+                                        uint32_t h = hash_home(x);
+                                        for (int p = 0; p < kHashProbes; ++p) {
+                                            if (atomicCAS(&s_hkey[h], -1, x) == -1) {
+                                                s_hval[h] = dx;
+                                                in_lds = true;
+                                                break;
+                                            }
+                                            h = (h + 1) & (kHashSlots - 1);
+                                        }
+                                        st8[x] = (uint8_t)(in_lds ? kS8Hash : kS8Global);
+                                        if (!in_lds) atomicAdd(&s_nslots, 1);
                                     }
                                 }
                             }
@@ -274,7 +344,12 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
                         }
                     } else {
                         rem[x] = pass;
-                        if (x < cap) st16[x] = (uint16_t)(d[j] > 0 ? kStNow : kStDead);
+                        if (x < cap) {
+                            if constexpr (SW == 16)
+                                st16[x] = (uint16_t)(d[j] > 0 ? kStNow : kStDead);
+                            else
+                                st8[x] = (uint8_t)(d[j] > 0 ? kS8Now : kS8Dead);
+                        }
                         if (d[j] > 0) {
                             alist[oa] = x;
                             apre[oa] = wo;
@@ -298,7 +373,7 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
             // Graphs whose state is all in LDS need only the barrier (one
             // workgroup owns a graph, and its plain stores and loads meet
             // in the CU's own cache).  The slot count is final after pass 1.
-            const bool dev_state = n > cap || s_nslots > kSlots;
+            const bool dev_state = n > cap || s_nslots > (SW == 16 ? kSlots : 0);
             if (dev_state) {
                 __threadfence();
                 __syncthreads();
@@ -429,8 +504,13 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
                     for (int j = 0; j < IT; ++j) {
                         const int32_t x = u[j];
                         const bool in = (uint32_t)x < (uint32_t)cap;
-                        const uint32_t st = st16[in ? x : 0];
-                        sv[j] = in ? st : kStDead;
+                        if constexpr (SW == 16) {
+                            const uint32_t st = st16[in ? x : 0];
+                            sv[j] = in ? st : kStDead;
+                        } else {
+                            const uint32_t st = st8[in ? x : 0];
+                            sv[j] = in ? st : kS8Dead;
+                        }
                     }
                     int32_t rv[IT];
 #pragma unroll
@@ -450,17 +530,34 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
                             ++badc;
                         } else if (x < cap) {
                             const uint32_t st = sv[j];
-                            if (st < kStSlot0) {
-                                atomicSub(&s_state[x >> 1], 1u << ((x & 1) << 4));
-                                ++cross;
-                            } else if (st < kStGlobal) {
-                                atomicSub(&s_big[st - kStSlot0], 1);
-                                ++cross;
-                            } else if (st == kStGlobal) {
-                                dec_global(gdeg + x);
-                                ++cross;
-                            } else if (st == kStNow) {
-                                ++intra;
+                            if constexpr (SW == 16) {
+                                if (st < kStSlot0) {
+                                    atomicSub(&s_state[x >> 1], 1u << ((x & 1) << 4));
+                                    ++cross;
+                                } else if (st < kStGlobal) {
+                                    atomicSub(&s_big[st - kStSlot0], 1);
+                                    ++cross;
+                                } else if (st == kStGlobal) {
+                                    dec_global(gdeg + x);
+                                    ++cross;
+                                } else if (st == kStNow) {
+                                    ++intra;
+                                }
+                            } else {
+                                // a degree is >= 1 before its decrement, so no
+                                // borrow crosses its byte
+                                if (st < kS8Hash) {
+                                    atomicSub(&s_state[x >> 2], 1u << ((x & 3) << 3));
+                                    ++cross;
+                                } else if (st == kS8Hash) {
+                                    atomicSub(&s_hval[hash_find(s_hkey, x)], 1);
+                                    ++cross;
+                                } else if (st == kS8Global) {
+                                    dec_global(gdeg + x);
+                                    ++cross;
+                                } else if (st == kS8Now) {
+                                    ++intra;
+                                }
                             }
                         } else if (rv[j] == kNever) {
                             dec_global(gdeg + x);
@@ -503,7 +600,12 @@ __global__ __launch_bounds__(NT) void k_batch_peel(BWork w, const int32_t* __res
                 for (int k = 0; k < 4; ++k) x[k] = alist[min(r + k * NT, nA - 1)];
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    if (r + k * NT < nA && x[k] < cap) st16[x[k]] = (uint16_t)kStDead;
+                    if (r + k * NT < nA && x[k] < cap) {
+                        if constexpr (SW == 16)
+                            st16[x[k]] = (uint16_t)kStDead;
+                        else
+                            st8[x[k]] = (uint8_t)kS8Dead;
+                    }
             }
         }
 
@@ -554,25 +656,25 @@ __global__ void k_batch_reset(BHead* head) {
 
 // ------------------------------------------------------------------ host
 
-using BatchFn = void (*)(BWork, const int32_t*, const int32_t*);
-
-template <int NT, int IT>
+template <int NT, int IT, int SW>
 hipError_t launch_one(const dsg_batch_plan* p, const BWork& w, const int32_t* rp,
                       const int32_t* ci, hipStream_t s) {
-    hipLaunchKernelGGL((k_batch_peel<NT, IT>), dim3(p->grid), dim3(NT), (size_t)p->lds_bytes, s,
-                       w, rp, ci);
+    hipLaunchKernelGGL((k_batch_peel<NT, IT, SW>), dim3(p->grid), dim3(NT), (size_t)p->lds_bytes,
+                       s, w, rp, ci);
     return hipGetLastError();
 }
 
-template <int NT, int IT>
+template <int NT, int IT, int SW>
 const void* kernel_ptr() {
-    return reinterpret_cast<const void*>(&k_batch_peel<NT, IT>);
+    return reinterpret_cast<const void*>(&k_batch_peel<NT, IT, SW>);
 }
 
-// Supported (block, walk_items) shapes (1024 x 16 would spill registers).
-const void* batch_kernel(int block, int items) {
-#define DSG_SHAPE(NT, IT) \
-    if (block == NT && items == IT) return kernel_ptr<NT, IT>();
+// Supported (block, walk_items) shapes (1024 x 16 would spill registers),
+// each with 16- and 8-bit vertex states.
+const void* batch_kernel(int block, int items, int bits) {
+#define DSG_SHAPE(NT, IT)                                   \
+    if (block == NT && items == IT)                         \
+        return bits == 8 ? kernel_ptr<NT, IT, 8>() : kernel_ptr<NT, IT, 16>();
     DSG_SHAPE(256, 4) DSG_SHAPE(256, 8) DSG_SHAPE(256, 16)
     DSG_SHAPE(512, 4) DSG_SHAPE(512, 8) DSG_SHAPE(512, 16)
     DSG_SHAPE(1024, 4) DSG_SHAPE(1024, 8)
@@ -582,8 +684,10 @@ const void* batch_kernel(int block, int items) {
 
 hipError_t batch_launch(const dsg_batch_plan* p, const BWork& w, const int32_t* rp,
                         const int32_t* ci, hipStream_t s) {
-#define DSG_SHAPE(NT, IT) \
-    if (p->block == NT && p->walk_items == IT) return launch_one<NT, IT>(p, w, rp, ci, s);
+#define DSG_SHAPE(NT, IT)                                            \
+    if (p->block == NT && p->walk_items == IT)                       \
+        return p->state_bits == 8 ? launch_one<NT, IT, 8>(p, w, rp, ci, s) \
+                                  : launch_one<NT, IT, 16>(p, w, rp, ci, s);
     DSG_SHAPE(256, 4) DSG_SHAPE(256, 8) DSG_SHAPE(256, 16)
     DSG_SHAPE(512, 4) DSG_SHAPE(512, 8) DSG_SHAPE(512, 16)
     DSG_SHAPE(1024, 4) DSG_SHAPE(1024, 8)
@@ -674,13 +778,13 @@ int32_t dsg_batch_prepare(const dsg_batch_graph* graphs, int32_t count, int64_t 
         if (launch->walk_items) items = launch->walk_items;
         grid = launch->grid;
     }
-    if (bpc < 1 || bpc > 8 || grid < 0 || !batch_kernel(block, items)) return DSG_EINVAL;
+    if (bpc < 1 || bpc > 8 || grid < 0 || !batch_kernel(block, items, 16)) return DSG_EINVAL;
 
     // per-graph checks, the device table and the queue order
     std::vector<BGraph> tab((size_t)count);
     std::vector<std::pair<int64_t, int64_t>> outs;
     outs.reserve((size_t)count);
-    int64_t tf_at = 0, entries = 0;
+    int64_t tf_at = 0, entries = 0, nmax = 0;
     for (int32_t i = 0; i < count; ++i) {
         const dsg_batch_graph& g = graphs[i];
         if (g.reserved != 0) return DSG_EINVAL;
@@ -703,6 +807,7 @@ int32_t dsg_batch_prepare(const dsg_batch_graph* graphs, int32_t count, int64_t 
         b.num = g.eps_num;
         b.den = g.eps_den;
         b.n = (int32_t)g.n;
+        nmax = std::max<int64_t>(nmax, g.n);
         b.m2 = (int32_t)(2 * g.m);
         b.max_pass = pass_bound(g.n, g.eps_num, g.eps_den);
         b.index = i;
@@ -721,17 +826,29 @@ int32_t dsg_batch_prepare(const dsg_batch_graph* graphs, int32_t count, int64_t 
     BDevInfo di;
     hipError_t e = batch_device_info(&di);
     if (e != hipSuccess) return map_hip(e);
-    const void* fn = batch_kernel(block, items);
-    hipFuncAttributes attr;
-    e = hipFuncGetAttributes(&attr, fn);
-    if (e != hipSuccess) return map_hip(e);
+    // LDS per workgroup left after the kernel's static tables, for the
+    // vertex states of each state width
     const int64_t budget = std::min<int64_t>(di.lds_per_block, di.lds_per_cu / bpc);
-    const int64_t dyn = ((budget - (int64_t)attr.sharedSizeBytes) / 4) * 4;
-    if (dyn < 4) return DSG_EINVAL;
-    // allow the largest request any plan of this kernel can make
-    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(di.lds_per_block - (int64_t)attr.sharedSizeBytes));
-    if (e != hipSuccess) return map_hip(e);
+    int64_t dyn_w[2] = {0, 0};  // 16-bit, 8-bit
+    for (int k = 0; k < 2; ++k) {
+        const void* fn = batch_kernel(block, items, k ? 8 : 16);
+        hipFuncAttributes attr;
+        e = hipFuncGetAttributes(&attr, fn);
+        if (e != hipSuccess) return map_hip(e);
+        dyn_w[k] = ((budget - (int64_t)attr.sharedSizeBytes) / 4) * 4;
+        // allow the largest request any plan of this kernel can make
+        e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(di.lds_per_block - (int64_t)attr.sharedSizeBytes));
+        if (e != hipSuccess) return map_hip(e);
+    }
+    if (dyn_w[0] < 4) return DSG_EINVAL;
+    // 16-bit states unless the largest graph needs more vertices than they
+    // hold and 8-bit states (one byte per vertex after a 32 KB hash table of
+    // large degrees) hold more
+    const int64_t cap16 = 2 * (dyn_w[0] / 4);
+    const int64_t cap8 = std::max<int64_t>(0, (dyn_w[1] - 8 * (int64_t)kHashSlots) & ~(int64_t)15);
+    const bool use8 = nmax > cap16 && cap8 > cap16;
+    const int64_t dyn = use8 ? dyn_w[1] : dyn_w[0];
 
     const BLayout L = batch_layout(count, entries, out_len);
     char* base = static_cast<char*>(workspace);
@@ -751,7 +868,8 @@ int32_t dsg_batch_prepare(const dsg_batch_graph* graphs, int32_t count, int64_t 
     const int64_t g_def = (int64_t)di.cus * bpc;
     plan->grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(grid ? grid : g_def, count));
     plan->lds_bytes = (int32_t)dyn;
-    plan->lds_vertices = (int32_t)std::min<int64_t>(2 * (dyn / 4), INT32_MAX);
+    plan->lds_vertices = (int32_t)std::min<int64_t>(use8 ? cap8 : cap16, INT32_MAX);
+    plan->state_bits = use8 ? 8 : 16;
     plan->out_len = out_len;
     plan->workspace = workspace;
     plan->ws_bytes = need;
@@ -782,6 +900,11 @@ int32_t dsg_batch_run(const dsg_batch_plan* plan, const int32_t* row_ptr, const 
     w.res = results;
     w.count = plan->count;
     w.cap = plan->lds_vertices;
+    w.state_bits = plan->state_bits;
+    if (w.state_bits != 16 && w.state_bits != 8) return DSG_EINVAL;
+    if (w.state_bits == 8 &&
+        (w.cap < 0 || (w.cap & 15) || (int64_t)w.cap + 8 * (int64_t)kHashSlots > plan->lds_bytes))
+        return DSG_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     k_batch_reset<<<1, 64, 0, s>>>(w.head);
     hipError_t e = hipGetLastError();

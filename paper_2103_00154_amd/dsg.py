@@ -88,7 +88,7 @@ class BatchLaunch(ctypes.Structure):
 class BatchPlan(ctypes.Structure):
     _fields_ = [("count", _I32), ("block", _I32), ("blocks_per_cu", _I32), ("grid", _I32),
                 ("walk_items", _I32), ("lds_bytes", _I32), ("lds_vertices", _I32),
-                ("reserved0", _I32), ("out_len", _I64), ("workspace", _P),
+                ("state_bits", _I32), ("out_len", _I64), ("workspace", _P),
                 ("ws_bytes", ctypes.c_uint64), ("reserved", _I64 * 4)]
 
 
@@ -423,7 +423,7 @@ class Batch:
         p = self.plan
         return {"block": p.block, "blocks_per_cu": p.blocks_per_cu, "grid": p.grid,
                 "walk_items": p.walk_items, "lds_bytes": p.lds_bytes,
-                "lds_vertices": p.lds_vertices}
+                "lds_vertices": p.lds_vertices, "state_bits": p.state_bits}
 
     def run(self, row_ptr, col_idx, *, best_ids=None, removed_at=None, results=None,
             stream=None):

@@ -195,3 +195,32 @@ def test_wave_tiles_over_many_short_rows():
     for launch in (None, {"block": 256, "walk_items": 16}, {"block": 1024, "walk_items": 4},
                    {"block": 512, "walk_items": 4}):
         check_batch(b, launch=launch, want=want)
+
+
+def test_eight_bit_states_with_hubs_and_a_full_hash_table():
+    # the largest graph exceeds the 16-bit states, so the plan takes 8-bit
+    # states: degrees of 240 and more go to the LDS hash table, and the dense
+    # graph has far more of them than the table's 4096 slots (the rest keep
+    # their degree in device memory)
+    from paper_2103_00154_amd import dsg
+    small = inputs.make_batch(inputs.batch_specs(8, seed=3, n_range=(100, 2000)))
+    tab, _ = dsg.batch_table(small.n, small.m, small.rp_off, small.ci_off, small.out_off, (1, 10))
+    assert dsg.Batch(tab, small.count, len(small.row_ptr), len(small.col_idx),
+                     small.out_len).shape["state_bits"] == 16
+    dense = inputs.erdos_renyi(80_000, 10_400_000, 31)
+    assert (dense.degrees() >= 240).sum() > 4096
+    hubs = inputs.chung_lu(99_000, 48, 2.1, seed=32)
+    gs = [dense, hubs, inputs.erdos_renyi(3000, 9000, 33), inputs.empty(5),
+          inputs.chung_lu(20_000, 30, 2.3, seed=34)]
+    b = inputs.concat(gs)
+    want = oracle_all(b)
+    plan, _ = check_batch(b, (0, 1))
+    assert plan.shape["state_bits"] == 8 and plan.shape["lds_vertices"] >= 99_000, plan.shape
+    # every shape with one workgroup per CU holds 8-bit states for more
+    # vertices than 16-bit ones
+    for launch in SHAPES:
+        if launch.get("blocks_per_cu", 1) != 1:
+            continue
+        plan, _ = check_batch(b, launch=launch, want=want)
+        assert plan.shape["state_bits"] == 8, plan.shape
+        say(f"8-bit plan: {plan.shape}")
