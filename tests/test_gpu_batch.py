@@ -139,15 +139,21 @@ def test_contract_violations_are_reported_per_graph():
     assert [r["status"] for r in results[1:]] == [dsg.DSG_EINVAL] * 3
 
 
-def test_hip_graph_capture_and_replay():
+@pytest.mark.parametrize("large", [False, True], ids=["16-bit", "8-bit"])
+def test_hip_graph_capture_and_replay(large):
     import torch
     from paper_2103_00154_amd import dsg
     b = inputs.make_batch(inputs.batch_specs(64, seed=9, n_range=(100, 30_000)))
+    if large:
+        # a graph above the 16-bit LDS states: the plan takes 8-bit states
+        b = inputs.concat([b.graph(i) for i in range(b.count)] +
+                          [inputs.chung_lu(95_000, 40, 2.1, seed=10)])
     want = oracle_all(b)
     rp = torch.from_numpy(b.row_ptr).cuda()
     ci = torch.from_numpy(b.col_idx).cuda()
     tab, count = dsg.batch_table(b.n, b.m, b.rp_off, b.ci_off, b.out_off, (1, 10))
     plan = dsg.Batch(tab, count, len(b.row_ptr), len(b.col_idx), b.out_len)
+    assert plan.shape["state_bits"] == (8 if large else 16)
     best = torch.full((b.out_len,), -1, dtype=torch.int32, device="cuda")
     res = torch.zeros((count, dsg.RESULT_WORDS), dtype=torch.int64, device="cuda")
     plan.run(rp, ci, best_ids=best, results=res)  # eager run before capture
