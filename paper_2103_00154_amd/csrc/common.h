@@ -33,6 +33,7 @@ constexpr int kApplyBatch = 16;                  // record loads per lane before
 constexpr int kApplyTiles = 4096;                // tiles whose run bounds k_apply stages in LDS
 constexpr int64_t kChunkMin = 8192;              // least records per apply work item
 constexpr int64_t kTargetItems = 512;            // apply work items aimed for per pass
+constexpr int64_t kDirectRecords = 65536;        // at most this many records: counts applied by atomics
 
 // Survivor filter of the walk: when a pass leaves at most kFiltBits
 // survivors, a bitmap with the bit of hash(id) set for every survivor is
@@ -96,6 +97,7 @@ struct alignas(256) DevState {
     int32_t apply_lanes;  // lanes that share one tile's run in k_apply (4..64)
     int32_t reduce_lanes; // lanes that share one rank in k_reduce (1..16)
     int32_t use_filt;     // 1: this pass's survivors are in the walk's survivor filter
+    int32_t apply_direct; // 1: few records; k_apply decrements the degrees itself, k_reduce idles
     // k-core levels (CBDS-P phase 1): the threshold is the level k and stays
     // there while passes remove vertices; a pass that removes none ends the
     // level, and the next level is the least degree left

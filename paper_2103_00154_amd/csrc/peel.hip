@@ -190,6 +190,7 @@ __global__ void k_init_state(Work w, const int32_t* __restrict__ rp, int64_t n, 
     st->apply_lanes = 64;
     st->reduce_lanes = 16;
     st->use_filt = 0;
+    st->apply_direct = 0;
     if (rp[0] != 0 || (int64_t)rp[n] != 2 * m) {
         st->status = kStBadRowPtr;
         st->done = 1;
@@ -751,7 +752,10 @@ __device__ void finish_pass(const Work& w, int32_t* s_flag, int32_t* red) {
     // surviving neighbour): every partial count would be zero, so the apply
     // kernels have nothing to do
     if (!*s_flag || st->cross == 0) {
-        if (threadIdx.x == 0) st->n_items = 0;
+        if (threadIdx.x == 0) {
+            st->n_items = 0;
+            st->apply_direct = 0;
+        }
         return;
     }
     const int32_t nb = st->nbins;
@@ -798,11 +802,20 @@ __device__ void finish_pass(const Work& w, int32_t* s_flag, int32_t* red) {
             } else {
                 st->n_items = (int32_t)total_a;
             }
+            // few records (light k-core levels, the last passes of a peel):
+            // partial rows and their reduction would cost the whole
+            // survivor range, the nonzero counts at most a few thousand
+            // device atomics (one per rank and item, however many records
+            // a hub receives)
+            st->apply_direct = (int64_t)st->cross <= kDirectRecords ? 1 : 0;
         }
         return;
     }
     // records sit in bin regions: split every bin into items of <= chunk records
-    if (threadIdx.x == 0) st->reduce_lanes = 16;
+    if (threadIdx.x == 0) {
+        st->reduce_lanes = 16;
+        st->apply_direct = 0;
+    }
     const int64_t ch = st->chunk;
     const int32_t per = (nb + kBlock - 1) / kBlock;
     const int32_t lo = std::min<int32_t>(nb, per * (int32_t)threadIdx.x);
@@ -1150,6 +1163,11 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply(Work w) {
     __shared__ int32_t cnt[kBinWidth];
     __shared__ uint32_t se[kApplyTiles];  // (start | end << 16) of a tile's run
     const uint16_t* __restrict__ recs = w.recs;
+    // few records: the item subtracts its nonzero counts from the degrees
+    // itself (one device atomic per rank and item), so that no partial row
+    // is written and k_reduce has nothing to do
+    const bool direct = st->apply_direct != 0;
+    int32_t* __restrict__ deg = deg_in(w, st->pass);  // the pass counter has advanced
     const int lanes = st->apply_lanes;
     const int groups = kApplyBlock / lanes;
     const int grp = threadIdx.x / lanes;
@@ -1203,8 +1221,18 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply(Work w) {
             for (; e < z; e += kApplyBlock) atomicAdd(&cnt[recs[e]], 1);
         }
         __syncthreads();
-        int32_t* __restrict__ out = w.partial + (int64_t)it * stride;
-        for (int i = threadIdx.x; i < ranks; i += kApplyBlock) out[i] = cnt[i];
+        if (direct) {
+            const int64_t rank0 = (int64_t)item.x << kBinShift;
+            for (int i = threadIdx.x; i < ranks; i += kApplyBlock) {
+                const int32_t c = cnt[i];
+                if (c)
+                    __hip_atomic_fetch_sub(deg + rank0 + i, c, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+            }
+        } else {
+            int32_t* __restrict__ out = w.partial + (int64_t)it * stride;
+            for (int i = threadIdx.x; i < ranks; i += kApplyBlock) out[i] = cnt[i];
+        }
         __syncthreads();
     }
 }
@@ -1215,7 +1243,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply(Work w) {
 
 __global__ __launch_bounds__(kBlock) void k_reduce(Work w) {
     const DevState* st = w.st;
-    if (st->n_items == 0) return;
+    if (st->n_items == 0 || st->apply_direct) return;
     const int64_t nL = st->nL;
     const int32_t stride = st->part_stride;
     // `lanes` lanes of a wave share one rank (1..16); within the wave the
@@ -2125,15 +2153,17 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
         int32_t* flag = w.list0;
         int32_t* elist = w.list1;
         int32_t* llist = w.deg0;
+        // every vertex again: the grid for the whole graph, not the one the
+        // level loop shrank to its last live sets
+        const unsigned full = default_grids(di, n, m, launch).mark;
         DSG_HIP(log.begin(kKindExtract));
         k_cbds_eligible<<<init_grid, kBlock, 0, s>>>(w, n, flag, elist);
-        k_cbds_legits<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, g->col_idx, n, flag, elist,
-                                                   llist);
-        k_cbds_pairs<<<mark_grid, kBlock, 0, s>>>(w, g->row_ptr, g->col_idx, n, flag, llist);
+        k_cbds_legits<<<full, kBlock, 0, s>>>(w, g->row_ptr, g->col_idx, n, flag, elist, llist);
+        k_cbds_pairs<<<full, kBlock, 0, s>>>(w, g->row_ptr, g->col_idx, n, flag, llist);
         if (best_ids) {
-            k_extract_count<<<mark_grid, kBlock, 0, s>>>(w, n, flag);
+            k_extract_count<<<full, kBlock, 0, s>>>(w, n, flag);
             k_scan_tiles<<<1, kScanBlock, 0, s>>>(w, 1, n, 0);
-            k_extract_scatter<<<mark_grid, kBlock, 0, s>>>(w, n, best_ids, flag);
+            k_extract_scatter<<<full, kBlock, 0, s>>>(w, n, best_ids, flag);
         }
         DSG_HIP(hipGetLastError());
         DSG_HIP(log.end());
