@@ -88,7 +88,7 @@ typedef struct {
  * depend on these. */
 typedef struct {
     int32_t mark_grid;  /* workgroups of the mark / extract kernels */
-    int32_t walk_grid;  /* workgroups of the neighbour-walk kernel (at most 4096 are used) */
+    int32_t walk_grid;  /* workgroups of the neighbour-walk kernels (at most 4096 are used) */
     int32_t pass_batch; /* 0: a peel runs one pass ahead of the device (each
                          * pass's tile scan posts to a pinned host word whether
                          * the pass leaves survivors, and the host then
@@ -100,13 +100,24 @@ typedef struct {
 
 /* Keep degree-update records in per-bin regions (one device atomic per
  * record) instead of per-tile regions.  The library does this by itself when
- * a pass leaves more than 1024 * 32768 survivors; the flag forces it. */
+ * a pass leaves more than 1024 * 32768 survivors (and does not key the
+ * records by neighbour id); the flag forces it and turns the id keying off. */
 #define DSG_LAUNCH_BIN_REGIONS 1
 
 /* The tile scan posts no progress, so a peel running one pass ahead of the
  * device waits for a post that does not come: after 20 ms with the stream
  * idle it finishes with batches of passes.  For testing that path. */
 #define DSG_LAUNCH_NO_PROGRESS 2
+
+/* Degree-update records keyed by neighbour id.  In a pass that leaves more
+ * than 65536 survivors (graphs of at most 2^25 vertices, not CBDS-P), the
+ * walk writes every walked entry as its neighbour's position in a bucket of
+ * 32768 consecutive ids, and the degree update finds the survivors among
+ * them, instead of the walk looking up each neighbour's survivor rank.
+ * DSG_LAUNCH_ID_BUCKETS uses this in every such peel pass with a survivor,
+ * whatever the survivor count; DSG_LAUNCH_NO_ID_BUCKETS never uses it. */
+#define DSG_LAUNCH_ID_BUCKETS 4
+#define DSG_LAUNCH_NO_ID_BUCKETS 8
 
 /* Optional per-kernel timing, measured with HIP events on the call's stream
  * around every launch of the call (host struct, filled on return).  Launches

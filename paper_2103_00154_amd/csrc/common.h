@@ -35,6 +35,24 @@ constexpr int64_t kChunkMin = 8192;              // least records per apply work
 constexpr int64_t kTargetItems = 512;            // apply work items aimed for per pass
 constexpr int64_t kDirectRecords = 65536;        // at most this many records: counts applied by atomics
 
+// Neighbour-id buckets of the degree update (walk mode 2, passes that leave
+// more than kFiltBits survivors).  Bucket b holds the ids
+// [b * kIdWidth, (b + 1) * kIdWidth), i.e. kIdWords consecutive rank-directory
+// words.  The walk writes no survivor rank: every walked entry becomes a
+// 16-bit position inside its neighbour's bucket, sorted by bucket in LDS per
+// group of kIdGroupTiles walk tiles; the apply step counts the positions of
+// one bucket in LDS and resolves liveness and rank from the bucket's
+// directory words, staged once per work item.
+constexpr int kXcds = 8;                         // accelerator dies of an MI355X (one L2 each)
+constexpr int kIdShift = 15;
+constexpr int kIdWidth = 1 << kIdShift;          // ids per bucket: the k_apply counters
+constexpr int kIdWords = kIdWidth / 32;          // rank-directory words per bucket
+constexpr int kIdMaxBuckets = 1024;              // n <= 2^25
+constexpr int kIdGroupTiles = 8;                 // walk tiles per record group
+constexpr int kIdGroup = kIdGroupTiles * kWalkTile;  // adjacency entries per record group
+static_assert(kIdWidth == kBinWidth, "k_apply's counters serve both kinds of bins");
+static_assert(kIdGroup < 65536, "group offsets are 16-bit");
+
 // Survivor filter of the walk: when a pass leaves at most kFiltBits
 // survivors, a bitmap with the bit of hash(id) set for every survivor is
 // copied into each walk workgroup's LDS, and a neighbour whose bit is clear
@@ -91,13 +109,18 @@ struct alignas(256) DevState {
     int32_t n_items;    // apply work items of the current pass
     int32_t part_stride;  // ints per partial-count row (min(kBinWidth, n))
     int32_t max_items;  // capacity of the work-item table
-    int32_t walk_mode;  // 0: records in per-tile regions, 1: records in bin regions
+    int32_t walk_mode;  // 0: records in per-tile regions, 1: records in bin regions,
+                        // 2: neighbour-id positions in per-group regions
     int32_t toff_stride;  // entries per tile in the tile-offset table (bins + 1)
     int32_t force_bins;   // 1: always use bin regions (launch flag)
     int32_t apply_lanes;  // lanes that share one tile's run in k_apply (4..64)
     int32_t reduce_lanes; // lanes that share one rank in k_reduce (1..16)
     int32_t use_filt;     // 1: this pass's survivors are in the walk's survivor filter
     int32_t apply_direct; // 1: few records; k_apply decrements the degrees itself, k_reduce idles
+    int32_t id_mode;      // neighbour-id buckets: 0 when they pay, 1 whenever allowed, 2 never
+    int32_t id_nb;        // walk mode 2: buckets (ceil(n / kIdWidth))
+    int32_t id_groups;    //   record groups of the current pass
+    int32_t id_words;     //   rank-directory words (ceil(n / 32))
     // k-core levels (CBDS-P phase 1): the threshold is the level k and stays
     // there while passes remove vertices; a pass that removes none ends the
     // level, and the next level is the least degree left

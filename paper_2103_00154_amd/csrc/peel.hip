@@ -90,7 +90,8 @@ struct Work {
     int4* items;          // apply items: (bin, first record, end record, ranks)
     int32_t* partial;     // items x part_stride: per-item counts
     uint16_t* recs;       // walk tiles x kWalkTile: 16-bit local ranks
-    uint16_t* toff;       // walk tiles x (bins + 1): bin offsets inside each tile
+    uint16_t* toff;       // walk tiles x (bins + 1): bin offsets inside each tile (walk
+                          // mode 2: record groups x buckets, 32-bit run bounds)
     uint32_t* filt;       // kFiltWords: survivor filter of the current pass
     unsigned long long* wpart;  // kMaxWalkGrid: decrement records per walk workgroup
     PassRecord* trace;    // kTraceCap
@@ -151,7 +152,7 @@ __device__ inline void store8(int32_t* __restrict__ p, int64_t base, int64_t lim
 __global__ void k_init_state(Work w, const int32_t* __restrict__ rp, int64_t n, int64_t m,
                              int64_t num, int64_t den, int32_t max_pass, int32_t trace_cap,
                              int32_t part_stride, int32_t max_items, int32_t force_bins,
-                             int32_t core_mode) {
+                             int32_t id_mode, int32_t core_mode) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     DevState* st = w.st;
     st->S = n;
@@ -191,6 +192,10 @@ __global__ void k_init_state(Work w, const int32_t* __restrict__ rp, int64_t n, 
     st->reduce_lanes = 16;
     st->use_filt = 0;
     st->apply_direct = 0;
+    st->id_mode = id_mode;
+    st->id_nb = 0;
+    st->id_groups = 0;
+    st->id_words = 0;
     if (rp[0] != 0 || (int64_t)rp[n] != 2 * m) {
         st->status = kStBadRowPtr;
         st->done = 1;
@@ -523,7 +528,18 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode,
             st->min_surv = (int32_t)min(tmin, (uint32_t)INT32_MAX);
             st->n_tiles_walk = (int32_t)((te + kWalkTile - 1) / kWalkTile);
             st->nbins = (int32_t)((tl + kBinWidth - 1) >> kBinShift);
-            st->walk_mode = (st->nbins <= kNbLds && !st->force_bins) ? 0 : 1;
+            // Neighbour-id buckets when the survivor filter is off (more
+            // survivors than it holds): there every walked entry would
+            // otherwise gather its neighbour's rank-directory word.  Not for
+            // core levels (light passes) or forced bin regions.
+            const int64_t nb2 = (n + kIdWidth - 1) >> kIdShift;
+            const bool ids = !st->core_mode && !st->force_bins && st->id_mode != 2 && tl > 0 &&
+                             te > 0 && nb2 <= kIdMaxBuckets &&
+                             (st->id_mode == 1 || tl > kFiltBits);
+            st->walk_mode = ids ? 2 : (st->nbins <= kNbLds && !st->force_bins) ? 0 : 1;
+            st->id_nb = (int32_t)nb2;
+            st->id_groups = (int32_t)((te + kIdGroup - 1) / kIdGroup);
+            st->id_words = (int32_t)((n + 31) >> 5);
             st->toff_stride = st->nbins + 1;
             st->use_filt = filt ? 1 : 0;
             st->tot_live += items;
@@ -748,6 +764,8 @@ __device__ void finish_pass(const Work& w, int32_t* s_flag, int32_t* red) {
         *s_flag = keep;
     }
     __syncthreads();
+    // walk mode 2 completes the pass after its degree update
+    if (st->walk_mode == 2) return;
     // no records (a pass that removed nothing, or whose failures had no
     // surviving neighbour): every partial count would be zero, so the apply
     // kernels have nothing to do
@@ -865,10 +883,113 @@ __device__ inline int32_t lanes_below(unsigned long long mask) {
                                               __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Row base (CSR row start minus walk offset) of this thread's entries
+// j * kBlock + tid of the walk tile that starts at entry e0 and spans the
+// walk-list rows i0 .. i0 + c - 1.  A tile inside at most kFewRows rows
+// compares each position with the row starts (the same values in every
+// lane); a longer span builds an owner table in LDS: rows start at strictly
+// increasing offsets, so a running max over the start marks works (indices
+// < kWalkTile + 1 fit 16 bits; 8 per 16-byte word).  `clear` runs before the
+// table's first barrier, and in the short case before one barrier when
+// `sync_few` is set; the caller synchronises before own[] and bas[] are
+// written again.
+template <typename Clear>
+__device__ __forceinline__ void tile_row_bases(const Work& w, int32_t i0, int32_t c, uint32_t e0,
+                                               int32_t len, int32_t (&rb)[kWalkItems],
+                                               uint16_t* own, int32_t* bas, int32_t* red,
+                                               bool sync_few, Clear clear) {
+    const int tid = threadIdx.x;
+    const int32_t* __restrict__ aoff = w.aoff;
+    const int32_t* __restrict__ arow = w.arow;
+    if (c <= kFewRows) {
+        int32_t fo[kFewRows], fb[kFewRows];
+#pragma unroll
+        for (int r = 0; r < kFewRows; ++r) {
+            // rows past the span repeat the last one, which selects the same
+            const int32_t i = i0 + min(r, c - 1);
+            const int32_t ao = aoff[i];
+            fo[r] = ao - (int32_t)e0;
+            fb[r] = arow[i] - ao;
+        }
+#pragma unroll
+        for (int j = 0; j < kWalkItems; ++j) {
+            const int32_t p = min(j * kBlock + tid, len - 1);
+            int32_t b = fb[0];
+#pragma unroll
+            for (int r = 1; r < kFewRows; ++r) b = fo[r] <= p ? fb[r] : b;
+            rb[j] = b;
+        }
+        if (sync_few) {
+            clear();
+            __syncthreads();
+        }
+    } else {
+        constexpr int kQ = kWalkItems / 8;  // 16-byte words of own[] per thread
+        uint4* own4 = reinterpret_cast<uint4*>(own);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) own4[kQ * tid + q] = make_uint4(0u, 0u, 0u, 0u);
+        clear();
+        __syncthreads();
+        // rows in rounds of four per thread, every load of a round issued
+        // before any is used (indices clamped to the last row)
+        for (int32_t r0 = 0; r0 < c; r0 += 4 * kBlock) {
+            int32_t ao[4], ar[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int32_t i = min(r0 + q * kBlock + tid, c - 1);
+                ao[q] = aoff[i0 + i];
+                ar[q] = arow[i0 + i];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int32_t i = r0 + q * kBlock + tid;
+                if (i < c) {
+                    bas[i] = ar[q] - ao[q];
+                    const int32_t o = ao[q] - (int32_t)e0;
+                    if (o < len) own[o > 0 ? o : 0] = (uint16_t)i;
+                }
+            }
+        }
+        __syncthreads();
+        {
+            uint4 q4[kQ];
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) q4[q] = own4[kQ * tid + q];
+            uint32_t run = 0;
+            auto step = [&run](uint32_t x) {
+                const uint32_t lo = run = max(run, x & 0xFFFFu);
+                const uint32_t hi = run = max(run, x >> 16);
+                return lo | (hi << 16);
+            };
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                q4[q].x = step(q4[q].x);
+                q4[q].y = step(q4[q].y);
+                q4[q].z = step(q4[q].z);
+                q4[q].w = step(q4[q].w);
+            }
+            const uint32_t carry = (uint32_t)block_excl_max((int32_t)run, red, 0);
+            auto lift = [carry](uint32_t x) {
+                return max(x & 0xFFFFu, carry) | (max(x >> 16, carry) << 16);
+            };
+#pragma unroll
+            for (int q = 0; q < kQ; ++q)
+                own4[kQ * tid + q] = make_uint4(lift(q4[q].x), lift(q4[q].y), lift(q4[q].z),
+                                                lift(q4[q].w));
+        }
+        __syncthreads();
+
+#pragma unroll
+        for (int j = 0; j < kWalkItems; ++j) rb[j] = own[min(j * kBlock + tid, len - 1)];
+#pragma unroll
+        for (int j = 0; j < kWalkItems; ++j) rb[j] = bas[rb[j]];
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restrict__ ci,
                                                  uint32_t n, uint32_t nnz) {
     DevState* st = w.st;
-    if (st->done) return;
+    if (st->done || st->walk_mode == 2) return;
     const int32_t nA = (int32_t)st->nA;
     const uint32_t total = (uint32_t)st->edges;
     // no survivor: no decrement is possible and the rows need no walk
@@ -879,8 +1000,6 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
     const uint2* __restrict__ dir = w.dir;
     int32_t* __restrict__ bin_cur = w.bin_cur;
     uint16_t* __restrict__ recs = w.recs;
-    const int32_t* __restrict__ aoff = w.aoff;
-    const int32_t* __restrict__ arow = w.arow;
     const int tid = threadIdx.x;
     const bool filt = st->use_filt != 0;
 
@@ -912,97 +1031,12 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
         }
         const int32_t c = ihi - i0 + 1;
 
-        // 1. row base (CSR row start minus walk offset) of every entry.  A
-        //    tile inside at most kFewRows rows compares each position with
-        //    the row starts (the same values in every lane); a longer span
-        //    builds an owner table in LDS: rows start at strictly increasing
-        //    offsets, so a running max over the start marks works (indices
-        //    < kWalkTile + 1 fit 16 bits; 8 per 16-byte word).
+        // 1. row base (CSR row start minus walk offset) of every entry
         int32_t rb[kWalkItems];
-        if (c <= kFewRows) {
-            int32_t fo[kFewRows], fb[kFewRows];
-#pragma unroll
-            for (int r = 0; r < kFewRows; ++r) {
-                // rows past the span repeat the last one, which selects the same
-                const int32_t i = i0 + min(r, c - 1);
-                const int32_t ao = aoff[i];
-                fo[r] = ao - (int32_t)e0;
-                fb[r] = arow[i] - ao;
-            }
-#pragma unroll
-            for (int j = 0; j < kWalkItems; ++j) {
-                const int32_t p = min(j * kBlock + tid, len - 1);
-                int32_t b = fb[0];
-#pragma unroll
-                for (int r = 1; r < kFewRows; ++r) b = fo[r] <= p ? fb[r] : b;
-                rb[j] = b;
-            }
-            if (lds_bins && !one_bin) {
-                for (int b = tid; b < nb; b += kBlock) tcount[b] = 0;
-                __syncthreads();
-            }
-        } else {
-            constexpr int kQ = kWalkItems / 8;  // 16-byte words of own[] per thread
-            uint4* own4 = reinterpret_cast<uint4*>(own);
-#pragma unroll
-            for (int q = 0; q < kQ; ++q) own4[kQ * tid + q] = make_uint4(0u, 0u, 0u, 0u);
+        tile_row_bases(w, i0, c, e0, len, rb, own, bas, red, lds_bins && !one_bin, [&] {
             if (lds_bins)
                 for (int b = tid; b < nb; b += kBlock) tcount[b] = 0;
-            __syncthreads();
-            // rows in rounds of four per thread, every load of a round issued
-            // before any is used (indices clamped to the last row)
-            for (int32_t r0 = 0; r0 < c; r0 += 4 * kBlock) {
-                int32_t ao[4], ar[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int32_t i = min(r0 + q * kBlock + tid, c - 1);
-                    ao[q] = aoff[i0 + i];
-                    ar[q] = arow[i0 + i];
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int32_t i = r0 + q * kBlock + tid;
-                    if (i < c) {
-                        bas[i] = ar[q] - ao[q];
-                        const int32_t o = ao[q] - (int32_t)e0;
-                        if (o < len) own[o > 0 ? o : 0] = (uint16_t)i;
-                    }
-                }
-            }
-            __syncthreads();
-            {
-                uint4 q4[kQ];
-#pragma unroll
-                for (int q = 0; q < kQ; ++q) q4[q] = own4[kQ * tid + q];
-                uint32_t run = 0;
-                auto step = [&run](uint32_t x) {
-                    const uint32_t lo = run = max(run, x & 0xFFFFu);
-                    const uint32_t hi = run = max(run, x >> 16);
-                    return lo | (hi << 16);
-                };
-#pragma unroll
-                for (int q = 0; q < kQ; ++q) {
-                    q4[q].x = step(q4[q].x);
-                    q4[q].y = step(q4[q].y);
-                    q4[q].z = step(q4[q].z);
-                    q4[q].w = step(q4[q].w);
-                }
-                const uint32_t carry = (uint32_t)block_excl_max((int32_t)run, red, 0);
-                auto lift = [carry](uint32_t x) {
-                    return max(x & 0xFFFFu, carry) | (max(x >> 16, carry) << 16);
-                };
-#pragma unroll
-                for (int q = 0; q < kQ; ++q)
-                    own4[kQ * tid + q] = make_uint4(lift(q4[q].x), lift(q4[q].y), lift(q4[q].z),
-                                                    lift(q4[q].w));
-            }
-            __syncthreads();
-
-#pragma unroll
-            for (int j = 0; j < kWalkItems; ++j) rb[j] = own[min(j * kBlock + tid, len - 1)];
-#pragma unroll
-            for (int j = 0; j < kWalkItems; ++j) rb[j] = bas[rb[j]];
-        }
+        });
 
         // 2. neighbour ids (coalesced: consecutive lanes, consecutive
         //    entries), all loads issued before any is used, with clamped
@@ -1132,14 +1166,180 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
     if (tid == 0) w.wpart[blockIdx.x] = bc;
 }
 
-// Sums the walk workgroups' record counts and completes the pass: |V|, |E|,
-// the best graph, the next threshold and the apply work items.
-__global__ __launch_bounds__(kBlock) void k_walk_finish(Work w, int32_t parts) {
+// ------------------------------------------------------ walk: id buckets
+// Walk mode 2.  A workgroup takes groups of kIdGroupTiles consecutive walk
+// tiles.  Every walked entry with a valid neighbour id becomes one record,
+// the id's position inside its bucket; whether the neighbour survives is
+// left to k_apply, so no entry gathers from the rank directory.  While the
+// group's tiles are walked, the entries are counted per bucket in LDS; the
+// counts' prefix then seeds one cursor per bucket, each entry takes its slot
+// from its bucket's cursor (the records sorted by bucket in LDS), and the
+// group stores them as one contiguous run (16-byte stores) with every
+// bucket's (start | end << 16) as its row of the offset table.
+
+__global__ __launch_bounds__(kBlock) void k_walk_ids(Work w, const int32_t* __restrict__ ci,
+                                                     uint32_t n, uint32_t nnz) {
+    DevState* st = w.st;
+    if (st->done || st->walk_mode != 2) return;
+    const int32_t nA = (int32_t)st->nA;
+    const uint32_t total = (uint32_t)st->edges;
+    const int32_t ntiles = st->n_tiles_walk;
+    const int32_t ngroups = st->id_groups;
+    const int32_t nb = st->id_nb;
+    const int tid = threadIdx.x;
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+    // the tiles' owner tables and the group's sorted records are never live
+    // at once and share their LDS
+    constexpr int kOwnBytes = 2 * kWalkTile, kBasBytes = 4 * (kWalkTile + 1);
+    constexpr int kPool = std::max(kOwnBytes + kBasBytes, 2 * kIdGroup);
+    __shared__ __align__(16) unsigned char pool[kPool];
+    uint16_t* own = reinterpret_cast<uint16_t*>(pool);
+    int32_t* bas = reinterpret_cast<int32_t*>(pool + kOwnBytes);
+    uint16_t* stage = reinterpret_cast<uint16_t*>(pool);
+    __shared__ int32_t hist[kIdMaxBuckets];  // bucket counts, then cursors
+    __shared__ int32_t red[kWaves];
+
+    for (int32_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        for (int b = tid; b < nb; b += kBlock) hist[b] = 0;
+        __syncthreads();
+        uint32_t key[kIdGroupTiles][kWalkItems];  // neighbour id, or kNone
+#pragma unroll
+        for (int s = 0; s < kIdGroupTiles; ++s) {
+#pragma unroll
+            for (int j = 0; j < kWalkItems; ++j) key[s][j] = kNone;
+            // every condition below is the same in the whole workgroup
+            const int32_t t = g * kIdGroupTiles + s;
+            if (t >= ntiles) continue;
+            const uint32_t e0 = (uint32_t)t * kWalkTile;
+            const int32_t len = (int32_t)min((uint32_t)kWalkTile, total - e0);
+            const int32_t i0 = w.tile_first[t];
+            const int32_t ihi = (t + 1 < ntiles) ? w.tile_first[t + 1] : nA - 1;
+            if (i0 < 0 || ihi >= nA || ihi < i0 || ihi - i0 + 1 > kWalkTile + 1) {
+                // cannot happen for a consistent walk list; never index with it
+                if (tid == 0) st->status = kStInvariant;
+                continue;
+            }
+            const int32_t c = ihi - i0 + 1;
+            int32_t rb[kWalkItems];
+            tile_row_bases(w, i0, c, e0, len, rb, own, bas, red, false, [] {});
+            // neighbour ids, all loads issued before any is used (clamped
+            // indices; lanes past the tile end re-read its last entry)
+            uint32_t u[kWalkItems];
+#pragma unroll
+            for (int j = 0; j < kWalkItems; ++j) {
+                const uint32_t p = (uint32_t)min(j * kBlock + tid, len - 1);
+                const uint32_t pos = min((uint32_t)rb[j] + e0 + p, nnz - 1u);
+                u[j] = (uint32_t)__builtin_nontemporal_load(ci + pos);
+            }
+#pragma unroll
+            for (int j = 0; j < kWalkItems; ++j) {
+                if (j * kBlock + tid >= len || u[j] >= n) u[j] = kNone;  // ids outside 0..n-1
+                if (u[j] != kNone) atomicAdd(&hist[u[j] >> kIdShift], 1);
+                key[s][j] = u[j];
+            }
+            __syncthreads();  // own[] and bas[] are rebuilt for the next tile
+        }
+        // bucket offsets: exclusive prefix of the counts, the group's row of
+        // the offset table, and the start of every bucket's cursor
+        int32_t all;
+        {
+            const int q = (nb + kBlock - 1) / kBlock;
+            const int b0 = min(nb, q * tid), b1 = min(nb, b0 + q);
+            int32_t sum = 0;
+            for (int b = b0; b < b1; ++b) sum += hist[b];
+            int32_t at = block_excl_sum(sum, red, &all);
+            uint32_t* __restrict__ to = reinterpret_cast<uint32_t*>(w.toff) + (int64_t)g * nb;
+            for (int b = b0; b < b1; ++b) {
+                const int32_t k = hist[b];
+                hist[b] = at;
+                to[b] = (uint32_t)at | ((uint32_t)(at + k) << 16);
+                at += k;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < kIdGroupTiles; ++s)
+#pragma unroll
+            for (int j = 0; j < kWalkItems; ++j)
+                if (key[s][j] != kNone)
+                    stage[atomicAdd(&hist[key[s][j] >> kIdShift], 1)] =
+                        (uint16_t)(key[s][j] & (kIdWidth - 1));
+        __syncthreads();
+        {
+            const uint4* src = reinterpret_cast<const uint4*>(stage);
+            uint4* __restrict__ dst = reinterpret_cast<uint4*>(w.recs + (int64_t)g * kIdGroup);
+            for (int i = tid; i < (all + 7) / 8; i += kBlock) dst[i] = src[i];
+        }
+        __syncthreads();  // hist[] and the pool are reused by the next group
+    }
+}
+
+// Walk mode 2: the apply work items, planned after the walk.  Bucket b gets
+// one item and its share of up to kTargetItems more, in proportion to the
+// adjacency entries of its ids (which bound its records and track them);
+// each item covers a contiguous range of the pass's record groups.  A bucket
+// with one item lets it update the degrees itself.
+__device__ void plan_id_items(const Work& w, const int32_t* __restrict__ rp, int64_t n,
+                              int32_t* red) {
+    DevState* st = w.st;
+    const int32_t nb = st->id_nb;
+    const int64_t G = st->id_groups;
+    const int64_t tot = rp[n];
+    const int64_t cap = st->max_items;
+    const int64_t extra = std::max<int64_t>(0, std::min<int64_t>(kTargetItems, cap - nb));
+    const int q = (nb + kBlock - 1) / kBlock;
+    const int b0 = std::min(nb, q * (int)threadIdx.x), b1 = std::min(nb, b0 + q);
+    int32_t cnt = 0;
+    for (int b = b0; b < b1; ++b) {
+        const int64_t lo = (int64_t)b << kIdShift;
+        const int64_t deg = rp[std::min<int64_t>(n, lo + kIdWidth)] - rp[lo];
+        cnt += (int32_t)std::min<int64_t>(G, 1 + (tot > 0 ? extra * deg / tot : 0));
+    }
+    int32_t total;
+    int32_t first = block_excl_sum(cnt, red, &total);
+    if (total > cap) {  // cannot happen: nb + extra <= cap
+        if (threadIdx.x == 0) {
+            st->status = kStInvariant;
+            st->done = 1;
+            st->n_items = 0;
+        }
+        return;
+    }
+    for (int b = b0; b < b1; ++b) {
+        const int64_t lo = (int64_t)b << kIdShift;
+        const int64_t deg = rp[std::min<int64_t>(n, lo + kIdWidth)] - rp[lo];
+        const int32_t k = (int32_t)std::min<int64_t>(G, 1 + (tot > 0 ? extra * deg / tot : 0));
+        const int32_t npos = (int32_t)std::min<int64_t>(kIdWidth, n - lo);
+        w.bin_items[b] = make_int2(first, k);
+        for (int32_t j = 0; j < k; ++j)
+            w.items[first + j] = make_int4(b, (int)(G * j / k), (int)(G * (j + 1) / k), npos);
+        first += k;
+    }
+    if (threadIdx.x == 0) {
+        st->n_items = total;
+        st->apply_direct = 0;
+    }
+}
+
+// Phase 0 (after the walk): sums the walk workgroups' record counts and
+// completes the pass: |V|, |E|, the best graph, the next threshold and the
+// apply work items; in walk mode 2 it only plans the work items.  Phase 1
+// (after the degree update): in walk mode 2, sums the apply workgroups'
+// counts of records that reached a survivor and completes the pass.
+__global__ __launch_bounds__(kBlock) void k_walk_finish(Work w, const int32_t* __restrict__ rp,
+                                                        int64_t n, int32_t parts, int32_t phase) {
     DevState* st = w.st;
     if (st->done) return;
     __shared__ int32_t red[kWaves];
     __shared__ unsigned long long redc[kWaves];
     __shared__ int32_t s_keep;
+    const bool ids = st->walk_mode == 2;
+    if (phase == 0 && ids) {
+        plan_id_items(w, rp, n, red);
+        return;
+    }
+    if (phase == 1 && !ids) return;
     unsigned long long c = 0;
     for (int32_t i = threadIdx.x; i < parts; i += kBlock) c += w.wpart[i];
     c = block_sum(c, redc);
@@ -1153,15 +1353,163 @@ __global__ __launch_bounds__(kBlock) void k_walk_finish(Work w, int32_t parts) {
 // range of a bin region): count them per rank in LDS and store the counts as
 // a partial row.
 
+// Walk mode 2: an item counts its bucket's records over its range of record
+// groups, then resolves every position from the bucket's rank-directory
+// words (staged once): a position whose live bit is set is a survivor, and
+// its count goes to that survivor's degree when the item is its bucket's
+// only one, else to the item's partial row at the position (k_reduce sums
+// the rows).  Counts that reach a survivor are this workgroup's part of the
+// pass's decrements.
+__device__ inline void count_chunk(uint4 q, int32_t k, int32_t s, int32_t e, int32_t* cnt) {
+    const uint32_t v[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+        const int32_t x = k * 8 + h;
+        if (x >= s && x < e) atomicAdd(&cnt[(v[h >> 1] >> ((h & 1) * 16)) & (kIdWidth - 1)], 1);
+    }
+}
+
+__device__ void apply_ids(const Work& w, int32_t* cnt, uint32_t* se, uint2* sdir,
+                          uint32_t* red32, unsigned long long* redc) {
+    constexpr int kNW = kApplyBlock / 64;
+    const DevState* st = w.st;
+    const int32_t n_items = st->n_items;
+    const int32_t stride = st->part_stride;
+    const int64_t nb = st->id_nb;
+    const uint32_t* __restrict__ toff2 = reinterpret_cast<const uint32_t*>(w.toff);
+    const int64_t nwords = st->id_words;
+    int32_t* __restrict__ deg = deg_out(w, st->pass);  // the pass completes after this update
+    const uint16_t* __restrict__ recs = w.recs;
+    const int tid = threadIdx.x;
+    unsigned long long cross = 0;
+    // Items are numbered by bucket, and one group region holds the runs of
+    // every bucket side by side, so items of neighbouring buckets read the
+    // same lines.  Workgroups are dispatched to the XCDs in turn (blockIdx.x
+    // modulo kXcds), each with its own L2: every XCD takes one contiguous
+    // eighth of the items.
+    const int xcds = gridDim.x % kXcds == 0 ? kXcds : 1;
+    const int32_t x = (int32_t)(blockIdx.x % xcds), per = (int32_t)(gridDim.x / xcds);
+    const int32_t it0 = (int32_t)((int64_t)n_items * x / xcds);
+    const int32_t it1 = (int32_t)((int64_t)n_items * (x + 1) / xcds);
+    for (int32_t it = it0 + (int32_t)(blockIdx.x / xcds); it < it1; it += per) {
+        const int4 item = w.items[it];
+        const int32_t b = item.x, npos = item.w;
+        const bool alone = w.bin_items[b].y == 1;
+        const int64_t w0 = (int64_t)b * kIdWords;
+        const int32_t nw = (int32_t)std::min<int64_t>(kIdWords, nwords - w0);
+        for (int i = tid; i < npos; i += kApplyBlock) cnt[i] = 0;
+        for (int i = tid; i < nw; i += kApplyBlock) sdir[i] = w.dir[w0 + i];
+        __syncthreads();
+        for (int64_t c0 = item.y; c0 < item.z; c0 += kApplyTiles) {
+            const int32_t cn = (int32_t)std::min<int64_t>(kApplyTiles, item.z - c0);
+            uint32_t len = 0;
+            {
+                // the run bounds of up to kApplyTiles groups, every load
+                // issued before any is stored (indices clamped to the last)
+                constexpr int kR = kApplyTiles / kApplyBlock;
+                uint32_t x[kR];
+#pragma unroll
+                for (int a = 0; a < kR; ++a)
+                    x[a] = toff2[(c0 + std::min(tid + a * kApplyBlock, cn - 1)) * nb + b];
+#pragma unroll
+                for (int a = 0; a < kR; ++a) {
+                    const int32_t i = tid + a * kApplyBlock;
+                    if (i < cn) {
+                        se[i] = x[a];
+                        len += (x[a] >> 16) - (x[a] & 0xFFFFu);
+                    }
+                }
+            }
+            // lanes per run: enough 8-record chunks, one per lane, for a
+            // mean run at any alignment; the lanes of a run load adjacent
+            // 16-byte chunks in one instruction.  Each group of lanes has
+            // kRuns runs in flight; the rest of a longer run follows in a loop.
+            const uint32_t all = block_sum<uint32_t, kNW>(len, red32);
+            int lanes = 1;
+            while (lanes < 64 && 8u * (uint32_t)lanes * (uint32_t)cn < all + 8u * (uint32_t)cn)
+                lanes *= 2;
+            const int groups = kApplyBlock / lanes, grp = tid / lanes, sub = tid % lanes;
+            constexpr int kRuns = 4;
+            for (int32_t i0 = grp; i0 < cn; i0 += kRuns * groups) {
+                const uint4* rr[kRuns];
+                int32_t rs[kRuns], re[kRuns], kk[kRuns];
+                uint4 q[kRuns];
+#pragma unroll
+                for (int a = 0; a < kRuns; ++a) {
+                    // past the last run, or past a run's end, the load
+                    // re-reads a chunk of the region (the run's first one)
+                    // and nothing outside a run is counted; an empty run may
+                    // start at the region's end
+                    const int32_t i = i0 + a * groups;
+                    const uint32_t xs = i < cn ? se[i] : 0u;
+                    rs[a] = (int32_t)(xs & 0xFFFFu);
+                    re[a] = (int32_t)(xs >> 16);
+                    rr[a] = reinterpret_cast<const uint4*>(
+                        recs + (c0 + std::min(i, cn - 1)) * (int64_t)kIdGroup);
+                    const int32_t k0 = std::min(rs[a] >> 3, kIdGroup / 8 - 1);
+                    kk[a] = k0 + sub;
+                    q[a] = rr[a][kk[a] * 8 < re[a] ? kk[a] : k0];
+                }
+#pragma unroll
+                for (int a = 0; a < kRuns; ++a) {
+                    count_chunk(q[a], kk[a], rs[a], re[a], cnt);
+                    for (int32_t k = kk[a] + lanes; k * 8 < re[a]; k += lanes)
+                        count_chunk(rr[a][k], k, rs[a], re[a], cnt);
+                }
+            }
+            __syncthreads();  // se is reloaded for the next groups; counts are done
+        }
+        // positions tid + k * kApplyBlock, eight at a time: the survivors'
+        // degrees are all loaded (unconditionally, rank 0 standing in for
+        // the other positions) before any is stored
+        static_assert(kIdWidth % (8 * kApplyBlock) == 0, "whole rounds of eight positions");
+        for (int p0 = tid; p0 < npos; p0 += 8 * kApplyBlock) {
+            int32_t c[8], r[8], dv[8];
+            bool live[8];
+#pragma unroll
+            for (int h = 0; h < 8; ++h) {
+                const int p = p0 + h * kApplyBlock;
+                const uint2 d = sdir[std::min(p, npos - 1) >> 5];
+                const uint32_t bit = 1u << (p & 31);
+                live[h] = p < npos && (d.x & bit);
+                c[h] = live[h] ? cnt[p] : 0;
+                r[h] = live[h] ? (int32_t)(d.y + __popc(d.x & (bit - 1u))) : 0;
+                cross += (uint32_t)c[h];
+            }
+            if (alone) {
+#pragma unroll
+                for (int h = 0; h < 8; ++h) dv[h] = deg[r[h]];
+#pragma unroll
+                for (int h = 0; h < 8; ++h)
+                    if (c[h]) deg[r[h]] = dv[h] - c[h];
+            } else {
+#pragma unroll
+                for (int h = 0; h < 8; ++h)
+                    if (live[h]) w.partial[(int64_t)it * stride + p0 + h * kApplyBlock] = c[h];
+            }
+        }
+        __syncthreads();  // cnt and sdir are reused by the next item
+    }
+    const unsigned long long all = block_sum<unsigned long long, kNW>(cross, redc);
+    if (tid == 0) w.wpart[blockIdx.x] = all;
+}
+
 __global__ __launch_bounds__(kApplyBlock) void k_apply(Work w) {
     const DevState* st = w.st;
+    __shared__ int32_t cnt[kBinWidth];
+    __shared__ uint32_t se[kApplyTiles];  // (start | end << 16) of a tile's run
+    __shared__ uint2 sdir[kIdWords];
+    __shared__ uint32_t red32[kApplyBlock / 64];
+    __shared__ unsigned long long redc[kApplyBlock / 64];
+    const int32_t mode = st->walk_mode;
+    if (mode == 2) {
+        apply_ids(w, cnt, se, sdir, red32, redc);
+        return;
+    }
     const int32_t n_items = st->n_items;
     if (n_items == 0) return;
     const int32_t stride = st->part_stride;
-    const int32_t mode = st->walk_mode;
     const int64_t tstride = st->toff_stride;
-    __shared__ int32_t cnt[kBinWidth];
-    __shared__ uint32_t se[kApplyTiles];  // (start | end << 16) of a tile's run
     const uint16_t* __restrict__ recs = w.recs;
     // few records: the item subtracts its nonzero counts from the degrees
     // itself (one device atomic per rank and item), so that no partial row
@@ -1246,6 +1594,25 @@ __global__ __launch_bounds__(kBlock) void k_reduce(Work w) {
     if (st->n_items == 0 || st->apply_direct) return;
     const int64_t nL = st->nL;
     const int32_t stride = st->part_stride;
+    if (st->walk_mode == 2) {
+        // walk mode 2: a survivor whose bucket has several items gets the
+        // sum of their partial rows at its position; the pass has not
+        // advanced yet
+        int32_t* __restrict__ deg = deg_out(w, st->pass);
+        const int32_t* __restrict__ lst = live_out(w, st->pass);
+        for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < nL;
+             r += (int64_t)gridDim.x * kBlock) {
+            const int32_t v = lst[r];
+            const int2 bi = w.bin_items[v >> kIdShift];
+            if (bi.y < 2) continue;
+            const int32_t* __restrict__ p =
+                w.partial + (int64_t)bi.x * stride + (v & (kIdWidth - 1));
+            int32_t sum = 0;
+            for (int32_t j = 0; j < bi.y; ++j) sum += p[(int64_t)j * stride];
+            if (sum) deg[r] -= sum;
+        }
+        return;
+    }
     // `lanes` lanes of a wave share one rank (1..16); within the wave the
     // 64 / lanes ranks are consecutive, so each partial row is read in runs
     const int lanes = st->reduce_lanes;
@@ -1733,6 +2100,7 @@ namespace {
 struct DevInfo {
     int cus = 0;
     int walk_blocks_per_cu = 0;
+    int walk_ids_blocks_per_cu = 0;
     int apply_blocks_per_cu = 0;
     bool ready = false;
 };
@@ -1757,11 +2125,15 @@ hipError_t device_info(DevInfo* out) {
         int per_apply = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_apply, k_apply, kApplyBlock, 0);
         if (e != hipSuccess) return e;
+        int per_ids = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_ids, k_walk_ids, kBlock, 0);
+        if (e != hipSuccess) return e;
         di.cus = cus;
         // more than 6 resident walk workgroups per CU measured slower (the
         // rank-directory gathers of extra tiles evict each other from L2)
         di.walk_blocks_per_cu = std::max(std::min(per, 6), 1);
         di.apply_blocks_per_cu = std::max(per_apply, 1);
+        di.walk_ids_blocks_per_cu = std::max(per_ids, 1);
         di.ready = true;
     }
     *out = di;
@@ -1771,6 +2143,22 @@ hipError_t device_info(DevInfo* out) {
 inline int64_t mark_tiles(int64_t n) { return (n + kMarkTile - 1) / kMarkTile + 1; }
 inline int64_t walk_tiles(int64_t m) { return (2 * m + kWalkTile - 1) / kWalkTile + 1; }
 inline int64_t max_bins(int64_t n) { return (n + kBinWidth - 1) / kBinWidth + 1; }
+inline int64_t id_groups(int64_t m) { return (2 * m + kIdGroup - 1) / kIdGroup + 1; }
+// neighbour-id buckets of walk mode 2, or 0 where the graph has too many ids
+inline int64_t id_buckets(int64_t n) {
+    const int64_t nb = (n + kIdWidth - 1) / kIdWidth;
+    return nb <= kIdMaxBuckets ? nb : 0;
+}
+// Whether a peel's passes may take walk mode 2 (the tile scan decides per
+// pass): never with forced bin regions or when the caller turns it off,
+// otherwise when the flag asks for it or more than kFiltBits vertices can
+// survive a pass.
+inline bool ids_allowed(int64_t n, const dsg_launch* launch) {
+    const int32_t f = launch ? launch->flags : 0;
+    if ((f & (DSG_LAUNCH_BIN_REGIONS | DSG_LAUNCH_NO_ID_BUCKETS)) || id_buckets(n) == 0)
+        return false;
+    return (f & DSG_LAUNCH_ID_BUCKETS) || n > kFiltBits;
+}
 inline int64_t part_stride(int64_t n) {
     return std::min<int64_t>(kBinWidth, std::max<int64_t>(n, 1));
 }
@@ -1819,8 +2207,10 @@ Layout layout(int64_t n, int64_t m) {
     L.bitems = take(8 * (size_t)nb);
     L.items = take(sizeof(int4) * (size_t)ni);
     L.partial = take(4 * (size_t)ni * (size_t)part_stride(n));
-    L.recs = take(2 * (size_t)walk_tiles(m) * kWalkTile);
-    L.toff = take(2 * (size_t)walk_tiles(m) * (size_t)(std::min<int64_t>(nb, kNbLds) + 1));
+    // per-tile regions and offsets, or per-group ones in walk mode 2
+    L.recs = take(2 * (size_t)std::max<int64_t>(walk_tiles(m) * kWalkTile, id_groups(m) * kIdGroup));
+    L.toff = take(std::max<size_t>(2 * (size_t)walk_tiles(m) * (std::min<int64_t>(nb, kNbLds) + 1),
+                                   4 * (size_t)id_groups(m) * id_buckets(n)));
     L.filt = take(4 * (size_t)kFiltWords);
     L.wpart = take(8 * (size_t)kMaxWalkGrid);
     L.trace = take(sizeof(PassRecord) * (size_t)kTraceCap);
@@ -1956,7 +2346,8 @@ Work make_work(char* base, const Layout& L, int32_t* removed_at) {
 
 // Grid sizes of one peel's kernels.
 struct Grids {
-    unsigned mark, walk, init, apply, reduce;
+    unsigned mark, walk, init, apply, reduce, walk_ids;
+    bool ids;  // the passes may take walk mode 2: its kernels are enqueued
 };
 
 Grids default_grids(const DevInfo& di, int64_t n, int64_t m, const dsg_launch* launch) {
@@ -1971,7 +2362,13 @@ Grids default_grids(const DevInfo& di, int64_t n, int64_t m, const dsg_launch* l
     gr.init = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>((int64_t)di.cus * 8, (n + kBlock - 1) / kBlock));
     gr.apply = (unsigned)std::max<int64_t>(
-        1, std::min<int64_t>((int64_t)di.cus * di.apply_blocks_per_cu, max_items(n, m)));
+        1, std::min<int64_t>({(int64_t)di.cus * di.apply_blocks_per_cu, max_items(n, m),
+                              (int64_t)kMaxWalkGrid}));
+    const int64_t ig = launch && launch->walk_grid ? launch->walk_grid
+                                                   : (int64_t)di.cus * di.walk_ids_blocks_per_cu;
+    gr.walk_ids = (unsigned)std::max<int64_t>(
+        1, std::min({ig, id_groups(m) - 1, (int64_t)kMaxWalkGrid}));
+    gr.ids = ids_allowed(n, launch);
     gr.reduce = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>((int64_t)di.cus * 8, (n * 16 + kBlock - 1) / kBlock));
     return gr;
@@ -1984,6 +2381,9 @@ hipError_t launch_init(const Work& w, const dsg_csr* g, int64_t n, int64_t m, in
                                   std::min(trace_cap, kTraceCap), (int32_t)part_stride(n),
                                   (int32_t)max_items(n, m),
                                   launch && (launch->flags & DSG_LAUNCH_BIN_REGIONS) ? 1 : 0,
+                                  core_mode || !ids_allowed(n, launch)               ? 2
+                                  : launch && (launch->flags & DSG_LAUNCH_ID_BUCKETS) ? 1
+                                                                                     : 0,
                                   core_mode);
     return hipGetLastError();
 }
@@ -2002,12 +2402,15 @@ hipError_t enqueue_pass(const Work& w, const Grids& gr, const dsg_csr* g, int64_
         (e = log.begin(kKindWalk)) != hipSuccess)
         return e;
     k_walk<<<gr.walk, kBlock, 0, s>>>(w, g->col_idx, (uint32_t)n, (uint32_t)(2 * m));
+    if (gr.ids)
+        k_walk_ids<<<gr.walk_ids, kBlock, 0, s>>>(w, g->col_idx, (uint32_t)n, (uint32_t)(2 * m));
     if ((e = hipGetLastError()) != hipSuccess || (e = log.end()) != hipSuccess ||
         (e = log.begin(kKindApply)) != hipSuccess)
         return e;
-    k_walk_finish<<<1, kBlock, 0, s>>>(w, (int32_t)gr.walk);
+    k_walk_finish<<<1, kBlock, 0, s>>>(w, g->row_ptr, n, (int32_t)gr.walk, 0);
     k_apply<<<gr.apply, kApplyBlock, 0, s>>>(w);
     k_reduce<<<gr.reduce, kBlock, 0, s>>>(w);
+    if (gr.ids) k_walk_finish<<<1, kBlock, 0, s>>>(w, g->row_ptr, n, (int32_t)gr.apply, 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return log.end();
 }
@@ -2046,7 +2449,8 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
     Work w;
     int32_t max_pass, batch;
     int64_t launched = 0;
-    unsigned mark_grid, walk_grid, init_grid, apply_grid, reduce_grid;
+    unsigned mark_grid, walk_grid, init_grid, apply_grid, reduce_grid, walk_ids_grid;
+    bool ids;
 
     DSG_HIP(device_info(&di));
     if (!t_host_state) {
@@ -2076,6 +2480,8 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
         init_grid = gr.init;
         apply_grid = gr.apply;
         reduce_grid = gr.reduce;
+        walk_ids_grid = gr.walk_ids;
+        ids = gr.ids && !core_mode;
         batch = launch && launch->pass_batch ? launch->pass_batch : std::min(max_pass, 8);
     }
 
@@ -2086,7 +2492,7 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
     {  // the scope of pass_launches, which the error paths jump past
     // One pass, seven launches; `seq` numbers it for the progress word.
     auto pass_launches = [&](int64_t seq) -> hipError_t {
-        const Grids gr{mark_grid, walk_grid, init_grid, apply_grid, reduce_grid};
+        const Grids gr{mark_grid, walk_grid, init_grid, apply_grid, reduce_grid, walk_ids_grid, ids};
         return enqueue_pass(w, gr, g, n, m, core_mode ? nullptr : best_ids, s, log, seq);
     };
 

@@ -54,6 +54,10 @@ class Launch(ctypes.Structure):
 #: dsg_launch.flags bit: keep degree-update records in per-bin regions
 LAUNCH_BIN_REGIONS = 1
 LAUNCH_NO_PROGRESS = 2
+#: dsg_launch.flags bits: degree-update records keyed by neighbour id in
+#: every pass that leaves survivors (graphs of at most 2^25 vertices), or never
+LAUNCH_ID_BUCKETS = 4
+LAUNCH_NO_ID_BUCKETS = 8
 
 
 class Profile(ctypes.Structure):
@@ -262,7 +266,9 @@ def peel(row_ptr, col_idx, eps=(1, 10), *, m: int | None = None, extract: bool =
         ln = Launch(int(launch.get("mark_grid", 0)), int(launch.get("walk_grid", 0)),
                     int(launch.get("pass_batch", 0)),
                     (LAUNCH_BIN_REGIONS if launch.get("bin_regions") else 0)
-                    | (LAUNCH_NO_PROGRESS if launch.get("no_progress") else 0))
+                    | (LAUNCH_NO_PROGRESS if launch.get("no_progress") else 0)
+                    | (LAUNCH_ID_BUCKETS if launch.get("id_buckets") is True else 0)
+                    | (LAUNCH_NO_ID_BUCKETS if launch.get("id_buckets") is False else 0))
     prof = Profile() if profile else None
     res = Result()
     with torch.cuda.device(dev):

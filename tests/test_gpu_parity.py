@@ -112,6 +112,16 @@ def test_families_across_tile_boundaries(dsg, gi):
         check(g, e)
 
 
+@pytest.mark.parametrize("gi", range(13))
+def test_id_bucket_walk_in_every_pass(dsg, gi):
+    # degree-update records keyed by neighbour id in every pass that leaves a
+    # survivor, whatever the survivor count: record groups of fewer than four
+    # walk tiles, buckets a group misses, a hub whose bucket takes most records
+    g = list(_tile_edge_graphs())[gi]
+    for e in [(0, 1), (1, 10), (1, 1)]:
+        check(g, e, launch={"id_buckets": True})
+
+
 def test_config_small_er(dsg):
     """Erdos-Renyi n=10,000, m=50,000, seed 0, eps=1/10."""
     g = inputs.erdos_renyi(10_000, 50_000, 0)
@@ -125,6 +135,9 @@ def test_config_rmat20(dsg, eps):
     g = _rmat20()
     check(g, eps)
     check(g, eps, launch={"bin_regions": True})
+    # the first passes leave more survivors than the walk's filter holds, so
+    # by default they key their records by neighbour id; here they do not
+    check(g, eps, launch={"id_buckets": False})
 
 
 _cache = {}
@@ -143,6 +156,8 @@ def _rmat20():
     # no progress posts: the peel waits out the 20 ms limit once, then
     # finishes with batches of passes
     {"no_progress": True}, {"no_progress": True, "walk_grid": 7},
+    {"id_buckets": True}, {"id_buckets": True, "walk_grid": 1},
+    {"id_buckets": True, "walk_grid": 5, "pass_batch": 1}, {"id_buckets": False},
 ])
 def test_launch_shape_does_not_change_results(dsg, launch):
     g = inputs.chung_lu(200_000, 24, 2.2, 12)
