@@ -318,13 +318,12 @@ def main() -> int:
         f"walk {walk_ms / args.steps:.3f} ms, apply {apply_ms / args.steps:.3f} ms, "
         f"mark {mark_ms / args.steps:.3f} ms")
 
-    # neighbour walk (the dominant kernel): algorithmic bytes = 4 B column id
-    # + 4 B neighbour state per walked entry (the method's own data); the
-    # design's intermediates - a 2 B record per degree decrement and 12 B per
-    # walk-list row (row start, prefix offset, owner) - are reported apart
-    # as overhead, not counted as algorithmic
+    # neighbour walk (the dominant kernel; one walk launch per pass, k_walk
+    # or, in passes that key their records by neighbour id, k_walk_ids):
+    # algorithmic bytes = 4 B column id + 4 B neighbour state per walked
+    # entry (the method's own data); the design's intermediates are reported
+    # apart as overhead, not counted as algorithmic (below)
     walk_bytes = 8 * walked
-    overhead = 2 * cross + 12 * walk_list
     per_launch_bytes = walk_bytes / walk_launches
     per_launch_ms = walk_ms / walk_launches
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
@@ -349,6 +348,13 @@ def main() -> int:
     for k, t in enumerate(pass_trace):
         log(f"{k + 1} {t['s_in']} {t['thresh']} {t['removed']} {t['walked']} {t['cross']} "
             f"{t['intra']} {t['e_out']}")
+    # the design's intermediates per walk launch: a 2 B record per degree
+    # decrement (per walked entry in a pass that keys its records by
+    # neighbour id: more than 65,536 survivors, at most 2^25 vertices) and
+    # 12 B per walk-list row (row start, prefix offset, owner)
+    records = sum(t["walked"] if t["s_out"] > 65536 and g.n <= 1 << 25 else t["cross"]
+                  for t in pass_trace)
+    overhead = 2 * records * args.steps + 12 * walk_list
 
     cpu = None
     parity = None
@@ -407,7 +413,7 @@ def main() -> int:
                    "launch": "library default", "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_walk",
+                     "traffic": traffic, "kernel": "k_walk / k_walk_ids (the walk of each pass)",
                      "launches_per_step": walk_launches // args.steps,
                      "ms_per_launch": round(per_launch_ms, 4),
                      "alg_bytes_per_launch": int(per_launch_bytes),

@@ -34,6 +34,24 @@
 //   k_reduce        subtracts every bin's partial rows from the survivors'
 //                   degrees (1 to 16 lanes per rank, by the rows per bin).
 //
+// A pass that leaves more survivors than the walk's survivor filter holds
+// keys its records by neighbour id instead (walk mode 2), so that no walked
+// entry gathers from the rank directory:
+//
+//   k_walk_ids      takes the walk list in groups of kIdGroupTiles tiles and
+//                   writes every walked entry as its neighbour's 16-bit
+//                   position in a bucket of kIdWidth consecutive ids, the
+//                   group's records sorted by bucket in LDS;
+//   k_walk_finish   (phase 0) plans the apply items: one to a few per
+//                   bucket, each over a range of record groups;
+//   k_apply         counts a bucket's positions in LDS, finds the survivors
+//                   among them from the bucket's rank-directory words and
+//                   subtracts their counts (or writes them as partial rows,
+//                   indexed by position, when a bucket has several items);
+//   k_reduce        sums those partial rows into the survivors' degrees;
+//   k_walk_finish   (phase 1) completes the pass (|V|, |E|, best, threshold)
+//                   from the counts that reached a survivor.
+//
 // The "barrier synchronization" between the two parts of Algorithm 1 is the
 // kernel boundary between k_mark_scatter and k_walk.  The degree decrements
 // of the paper's part 2 ("atomicSub" on the neighbour's degree) become
@@ -91,7 +109,7 @@ struct Work {
     int32_t* partial;     // items x part_stride: per-item counts
     uint16_t* recs;       // walk tiles x kWalkTile: 16-bit local ranks
     uint16_t* toff;       // walk tiles x (bins + 1): bin offsets inside each tile (walk
-                          // mode 2: record groups x buckets, 32-bit run bounds)
+                          // mode 2: buckets x record groups, 32-bit run bounds)
     uint32_t* filt;       // kFiltWords: survivor filter of the current pass
     unsigned long long* wpart;  // kMaxWalkGrid: decrement records per walk workgroup
     PassRecord* trace;    // kTraceCap
@@ -379,8 +397,13 @@ __device__ inline int scan_slot(int r) { return r + (r >> 5); }
 // the host sees it while the pass is still running): `seq` numbers the
 // passes the host has enqueued, `final` says that no pass after this one
 // has work, so the host enqueues no more.
-__device__ inline void post_progress(int64_t* p, int64_t seq, bool fin) {
-    __hip_atomic_store(p, 2 * seq + (fin ? 1 : 0), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+// The progress word: 4 seq + 2 few + fin, where fin says that pass seq left
+// no survivor (or that the peel had ended) and few that it left at most
+// kFiltBits survivors, so that no later pass can key its records by
+// neighbour id unless a launch flag forces it.
+__device__ inline void post_progress(int64_t* p, int64_t seq, bool fin, bool few) {
+    __hip_atomic_store(p, 4 * seq + (few ? 2 : 0) + (fin ? 1 : 0), __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode, int64_t n,
@@ -389,7 +412,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode,
     DevState* st = w.st;
     if (mode == 0) {
         if (st->done) {
-            if (threadIdx.x == 0 && w.progress) post_progress(w.progress, seq, true);
+            if (threadIdx.x == 0 && w.progress) post_progress(w.progress, seq, true, true);
             return;
         }
     } else {
@@ -548,7 +571,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode,
             w.aoff[ta] = (int32_t)te;
             w.bin_start[st->nbins] = (int32_t)tds;
             // a pass that leaves no survivor ends the run
-            if (w.progress) post_progress(w.progress, seq, tl == 0);
+            if (w.progress) post_progress(w.progress, seq, tl == 0, tl <= kFiltBits);
         } else {
             st->best_count = ta;
         }
@@ -1175,7 +1198,7 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
 // counts' prefix then seeds one cursor per bucket, each entry takes its slot
 // from its bucket's cursor (the records sorted by bucket in LDS), and the
 // group stores them as one contiguous run (16-byte stores) with every
-// bucket's (start | end << 16) as its row of the offset table.
+// bucket's (start | end << 16) in the group's column of the offset table.
 
 __global__ __launch_bounds__(kBlock) void k_walk_ids(Work w, const int32_t* __restrict__ ci,
                                                      uint32_t n, uint32_t nnz) {
@@ -1249,11 +1272,13 @@ __global__ __launch_bounds__(kBlock) void k_walk_ids(Work w, const int32_t* __re
             int32_t sum = 0;
             for (int b = b0; b < b1; ++b) sum += hist[b];
             int32_t at = block_excl_sum(sum, red, &all);
-            uint32_t* __restrict__ to = reinterpret_cast<uint32_t*>(w.toff) + (int64_t)g * nb;
+            // bucket-major (b * groups + g): k_apply reads a bucket's bounds
+            // over consecutive groups as one coalesced run
+            uint32_t* __restrict__ to = reinterpret_cast<uint32_t*>(w.toff) + g;
             for (int b = b0; b < b1; ++b) {
                 const int32_t k = hist[b];
                 hist[b] = at;
-                to[b] = (uint32_t)at | ((uint32_t)(at + k) << 16);
+                to[(int64_t)b * ngroups] = (uint32_t)at | ((uint32_t)(at + k) << 16);
                 at += k;
             }
         }
@@ -1360,12 +1385,17 @@ __global__ __launch_bounds__(kBlock) void k_walk_finish(Work w, const int32_t* _
 // only one, else to the item's partial row at the position (k_reduce sums
 // the rows).  Counts that reach a survivor are this workgroup's part of the
 // pass's decrements.
+// The eight records of chunk k (records 8k .. 8k + 7 of the group) that lie
+// in the run [s, e) are counted; the others go to this lane's spare counter
+// past the bucket's (no branch, and no two lanes share a spare).
 __device__ inline void count_chunk(uint4 q, int32_t k, int32_t s, int32_t e, int32_t* cnt) {
     const uint32_t v[4] = {q.x, q.y, q.z, q.w};
+    const uint32_t spare = kIdWidth + (uint32_t)lane_id();
+    const uint32_t off = (uint32_t)(k * 8 - s), len = (uint32_t)(e - s);
 #pragma unroll
     for (int h = 0; h < 8; ++h) {
-        const int32_t x = k * 8 + h;
-        if (x >= s && x < e) atomicAdd(&cnt[(v[h >> 1] >> ((h & 1) * 16)) & (kIdWidth - 1)], 1);
+        const uint32_t r = (v[h >> 1] >> ((h & 1) * 16)) & (kIdWidth - 1);
+        atomicAdd(&cnt[off + h < len ? r : spare], 1);
     }
 }
 
@@ -1375,7 +1405,7 @@ __device__ void apply_ids(const Work& w, int32_t* cnt, uint32_t* se, uint2* sdir
     const DevState* st = w.st;
     const int32_t n_items = st->n_items;
     const int32_t stride = st->part_stride;
-    const int64_t nb = st->id_nb;
+    const int64_t G = st->id_groups;
     const uint32_t* __restrict__ toff2 = reinterpret_cast<const uint32_t*>(w.toff);
     const int64_t nwords = st->id_words;
     int32_t* __restrict__ deg = deg_out(w, st->pass);  // the pass completes after this update
@@ -1410,7 +1440,7 @@ __device__ void apply_ids(const Work& w, int32_t* cnt, uint32_t* se, uint2* sdir
                 uint32_t x[kR];
 #pragma unroll
                 for (int a = 0; a < kR; ++a)
-                    x[a] = toff2[(c0 + std::min(tid + a * kApplyBlock, cn - 1)) * nb + b];
+                    x[a] = toff2[b * G + c0 + std::min(tid + a * kApplyBlock, cn - 1)];
 #pragma unroll
                 for (int a = 0; a < kR; ++a) {
                     const int32_t i = tid + a * kApplyBlock;
@@ -1429,10 +1459,9 @@ __device__ void apply_ids(const Work& w, int32_t* cnt, uint32_t* se, uint2* sdir
             while (lanes < 64 && 8u * (uint32_t)lanes * (uint32_t)cn < all + 8u * (uint32_t)cn)
                 lanes *= 2;
             const int groups = kApplyBlock / lanes, grp = tid / lanes, sub = tid % lanes;
-            constexpr int kRuns = 4;
+            constexpr int kRuns = 8;
             for (int32_t i0 = grp; i0 < cn; i0 += kRuns * groups) {
-                const uint4* rr[kRuns];
-                int32_t rs[kRuns], re[kRuns], kk[kRuns];
+                uint32_t xs[kRuns];
                 uint4 q[kRuns];
 #pragma unroll
                 for (int a = 0; a < kRuns; ++a) {
@@ -1441,20 +1470,24 @@ __device__ void apply_ids(const Work& w, int32_t* cnt, uint32_t* se, uint2* sdir
                     // and nothing outside a run is counted; an empty run may
                     // start at the region's end
                     const int32_t i = i0 + a * groups;
-                    const uint32_t xs = i < cn ? se[i] : 0u;
-                    rs[a] = (int32_t)(xs & 0xFFFFu);
-                    re[a] = (int32_t)(xs >> 16);
-                    rr[a] = reinterpret_cast<const uint4*>(
+                    xs[a] = i < cn ? se[i] : 0u;
+                    const int32_t rs = (int32_t)(xs[a] & 0xFFFFu), re = (int32_t)(xs[a] >> 16);
+                    const uint4* __restrict__ r = reinterpret_cast<const uint4*>(
                         recs + (c0 + std::min(i, cn - 1)) * (int64_t)kIdGroup);
-                    const int32_t k0 = std::min(rs[a] >> 3, kIdGroup / 8 - 1);
-                    kk[a] = k0 + sub;
-                    q[a] = rr[a][kk[a] * 8 < re[a] ? kk[a] : k0];
+                    const int32_t k0 = std::min(rs >> 3, kIdGroup / 8 - 1);
+                    q[a] = r[(k0 + sub) * 8 < re ? k0 + sub : k0];
                 }
 #pragma unroll
                 for (int a = 0; a < kRuns; ++a) {
-                    count_chunk(q[a], kk[a], rs[a], re[a], cnt);
-                    for (int32_t k = kk[a] + lanes; k * 8 < re[a]; k += lanes)
-                        count_chunk(rr[a][k], k, rs[a], re[a], cnt);
+                    const int32_t rs = (int32_t)(xs[a] & 0xFFFFu), re = (int32_t)(xs[a] >> 16);
+                    const int32_t k = std::min(rs >> 3, kIdGroup / 8 - 1) + sub;
+                    count_chunk(q[a], k, rs, re, cnt);
+                    if ((k + lanes) * 8 < re) {
+                        const uint4* __restrict__ r = reinterpret_cast<const uint4*>(
+                            recs + (c0 + i0 + a * groups) * (int64_t)kIdGroup);
+                        for (int32_t kx = k + lanes; kx * 8 < re; kx += lanes)
+                            count_chunk(r[kx], kx, rs, re, cnt);
+                    }
                 }
             }
             __syncthreads();  // se is reloaded for the next groups; counts are done
@@ -1496,7 +1529,7 @@ __device__ void apply_ids(const Work& w, int32_t* cnt, uint32_t* se, uint2* sdir
 
 __global__ __launch_bounds__(kApplyBlock) void k_apply(Work w) {
     const DevState* st = w.st;
-    __shared__ int32_t cnt[kBinWidth];
+    __shared__ int32_t cnt[kBinWidth + 64];  // (walk mode 2: one spare counter per lane)
     __shared__ uint32_t se[kApplyTiles];  // (start | end << 16) of a tile's run
     __shared__ uint2 sdir[kIdWords];
     __shared__ uint32_t red32[kApplyBlock / 64];
@@ -2388,8 +2421,9 @@ hipError_t launch_init(const Work& w, const dsg_csr* g, int64_t n, int64_t m, in
     return hipGetLastError();
 }
 
-// One pass of Algorithm 1 as seven launches; `seq` numbers it for the
-// progress word (when w.progress is set).  `log` brackets the kernel groups
+// One pass of Algorithm 1 as seven launches, nine where the pass may key its
+// records by neighbour id (gr.ids); `seq` numbers it for the progress word
+// (when w.progress is set).  `log` brackets the kernel groups
 // with events when it is on.
 hipError_t enqueue_pass(const Work& w, const Grids& gr, const dsg_csr* g, int64_t n, int64_t m,
                         int32_t* best, hipStream_t s, EventLog& log, int64_t seq) {
@@ -2497,9 +2531,9 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
     };
 
     // Peeling passes run one pass ahead of the host: pass k's tile scan
-    // posts whether pass k leaves survivors, and the host enqueues pass k + 1
-    // on that, while pass k's walk and degree updates still run.  No pass is
-    // then enqueued after the last one.  Core levels (many light passes,
+    // posts whether pass k leaves survivors (and whether few), and the host
+    // enqueues pass k + 1 on that, while pass k's walk and degree updates
+    // still run.  No pass is then enqueued after the last one.  Core levels (many light passes,
     // grids resized between batches) and an explicit pass batch use batches
     // of passes with a host check after each; so does the rest of a peel
     // whose post did not come (the stream drained or failed first).
@@ -2510,8 +2544,11 @@ int32_t run_peel(const dsg_csr* g, int64_t n, int64_t m, int64_t eps_num, int64_
         for (int64_t seq = 1;; ++seq) {
             DSG_HIP(pass_launches(seq));
             ++launched;
-            const int64_t v = wait_progress(t_progress, 2 * seq, s);
+            const int64_t v = wait_progress(t_progress, 4 * seq, s);
             if (v < 0 || (v & 1) || launched > (int64_t)max_pass) break;
+            // survivors only decrease: after a pass with few, no later pass
+            // takes walk mode 2 by itself, and its kernels need not be queued
+            if ((v & 2) && !(launch && (launch->flags & DSG_LAUNCH_ID_BUCKETS))) ids = false;
         }
         w.progress = nullptr;
     }
