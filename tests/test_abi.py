@@ -61,6 +61,15 @@ def test_struct_layouts_match_header(tmp_path):
     assert got == want
 
 
+def test_launch_flags_match_the_header():
+    # the binding's flag bits are the header's #defines
+    text = (ROOT / "include" / "dsg.h").read_text()
+    defs = {k: int(v) for k, v in re.findall(r"#define DSG_LAUNCH_(\w+) (\d+)", text)}
+    assert defs == {"BIN_REGIONS": 1, "NO_PROGRESS": 2, "ID_BUCKETS": 4, "NO_ID_BUCKETS": 8}
+    for k, v in defs.items():
+        assert getattr(dsg, "LAUNCH_" + k) == v
+
+
 def test_workspace_bytes():
     h = dsg.lib()
     small = h.dsg_workspace_bytes(1000, 5000)
