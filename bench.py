@@ -350,10 +350,11 @@ def main() -> int:
             f"{t['intra']} {t['e_out']}")
     # the design's intermediates per walk launch: a 2 B record per degree
     # decrement (per walked entry in a pass that keys its records by
-    # neighbour id: more than 65,536 survivors, at most 2^25 vertices) and
-    # 12 B per walk-list row (row start, prefix offset, owner)
-    records = sum(t["walked"] if t["s_out"] > 65536 and g.n <= 1 << 25 else t["cross"]
-                  for t in pass_trace)
+    # neighbour id: more than 65,536 survivors, at least 2^25 walked entries,
+    # at most 2^25 vertices) and 12 B per walk-list row (row start, prefix
+    # offset, owner)
+    records = sum(t["walked"] if t["s_out"] > 65536 and t["walked"] >= 1 << 25
+                  and g.n <= 1 << 25 else t["cross"] for t in pass_trace)
     overhead = 2 * records * args.steps + 12 * walk_list
 
     cpu = None

@@ -110,12 +110,13 @@ typedef struct {
 #define DSG_LAUNCH_NO_PROGRESS 2
 
 /* Degree-update records keyed by neighbour id.  In a pass that leaves more
- * than 65536 survivors (graphs of at most 2^25 vertices, not CBDS-P), the
- * walk writes every walked entry as its neighbour's position in a bucket of
- * 32768 consecutive ids, and the degree update finds the survivors among
- * them, instead of the walk looking up each neighbour's survivor rank.
- * DSG_LAUNCH_ID_BUCKETS uses this in every such peel pass with a survivor,
- * whatever the survivor count; DSG_LAUNCH_NO_ID_BUCKETS never uses it. */
+ * than 65536 survivors and walks at least 2^25 adjacency entries (graphs of
+ * at most 2^25 vertices, not CBDS-P), the walk writes every walked entry as
+ * its neighbour's position in a bucket of 32768 consecutive ids, and the
+ * degree update finds the survivors among them, instead of the walk looking
+ * up each neighbour's survivor rank.  DSG_LAUNCH_ID_BUCKETS uses this in
+ * every peel pass that leaves a survivor, whatever the survivor count and
+ * walk length; DSG_LAUNCH_NO_ID_BUCKETS never uses it. */
 #define DSG_LAUNCH_ID_BUCKETS 4
 #define DSG_LAUNCH_NO_ID_BUCKETS 8
 

@@ -48,6 +48,7 @@ constexpr int kIdShift = 15;
 constexpr int kIdWidth = 1 << kIdShift;          // ids per bucket: the k_apply counters
 constexpr int kIdWords = kIdWidth / 32;          // rank-directory words per bucket
 constexpr int kIdMaxBuckets = 1024;              // n <= 2^25
+constexpr int64_t kIdMinEntries = int64_t(1) << 25;  // least walk entries of an id-keyed pass
 constexpr int kIdGroupTiles = 8;                 // walk tiles per record group
 constexpr int kIdGroup = kIdGroupTiles * kWalkTile;  // adjacency entries per record group
 static_assert(kIdWidth == kBinWidth, "k_apply's counters serve both kinds of bins");

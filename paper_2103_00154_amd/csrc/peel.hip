@@ -552,13 +552,16 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(Work w, int32_t mode,
             st->n_tiles_walk = (int32_t)((te + kWalkTile - 1) / kWalkTile);
             st->nbins = (int32_t)((tl + kBinWidth - 1) >> kBinShift);
             // Neighbour-id buckets when the survivor filter is off (more
-            // survivors than it holds): there every walked entry would
-            // otherwise gather its neighbour's rank-directory word.  Not for
-            // core levels (light passes) or forced bin regions.
+            // survivors than it holds) and the walk is long: there every
+            // walked entry would otherwise gather its neighbour's
+            // rank-directory word, and the saving repays the id-keyed pass's
+            // fixed costs (its apply items and two more launches; measured
+            // to break even near 2^25 entries).  Not for core levels (light
+            // passes) or forced bin regions.
             const int64_t nb2 = (n + kIdWidth - 1) >> kIdShift;
             const bool ids = !st->core_mode && !st->force_bins && st->id_mode != 2 && tl > 0 &&
                              te > 0 && nb2 <= kIdMaxBuckets &&
-                             (st->id_mode == 1 || tl > kFiltBits);
+                             (st->id_mode == 1 || (tl > kFiltBits && te >= kIdMinEntries));
             st->walk_mode = ids ? 2 : (st->nbins <= kNbLds && !st->force_bins) ? 0 : 1;
             st->id_nb = (int32_t)nb2;
             st->id_groups = (int32_t)((te + kIdGroup - 1) / kIdGroup);
@@ -2184,13 +2187,13 @@ inline int64_t id_buckets(int64_t n) {
 }
 // Whether a peel's passes may take walk mode 2 (the tile scan decides per
 // pass): never with forced bin regions or when the caller turns it off,
-// otherwise when the flag asks for it or more than kFiltBits vertices can
-// survive a pass.
-inline bool ids_allowed(int64_t n, const dsg_launch* launch) {
+// otherwise when the flag asks for it, or when more than kFiltBits vertices
+// can survive a pass and a pass can walk kIdMinEntries entries.
+inline bool ids_allowed(int64_t n, int64_t m, const dsg_launch* launch) {
     const int32_t f = launch ? launch->flags : 0;
     if ((f & (DSG_LAUNCH_BIN_REGIONS | DSG_LAUNCH_NO_ID_BUCKETS)) || id_buckets(n) == 0)
         return false;
-    return (f & DSG_LAUNCH_ID_BUCKETS) || n > kFiltBits;
+    return (f & DSG_LAUNCH_ID_BUCKETS) || (n > kFiltBits && 2 * m >= kIdMinEntries);
 }
 inline int64_t part_stride(int64_t n) {
     return std::min<int64_t>(kBinWidth, std::max<int64_t>(n, 1));
@@ -2401,7 +2404,7 @@ Grids default_grids(const DevInfo& di, int64_t n, int64_t m, const dsg_launch* l
                                                    : (int64_t)di.cus * di.walk_ids_blocks_per_cu;
     gr.walk_ids = (unsigned)std::max<int64_t>(
         1, std::min({ig, id_groups(m) - 1, (int64_t)kMaxWalkGrid}));
-    gr.ids = ids_allowed(n, launch);
+    gr.ids = ids_allowed(n, m, launch);
     gr.reduce = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>((int64_t)di.cus * 8, (n * 16 + kBlock - 1) / kBlock));
     return gr;
@@ -2414,7 +2417,7 @@ hipError_t launch_init(const Work& w, const dsg_csr* g, int64_t n, int64_t m, in
                                   std::min(trace_cap, kTraceCap), (int32_t)part_stride(n),
                                   (int32_t)max_items(n, m),
                                   launch && (launch->flags & DSG_LAUNCH_BIN_REGIONS) ? 1 : 0,
-                                  core_mode || !ids_allowed(n, launch)               ? 2
+                                  core_mode || !ids_allowed(n, m, launch)            ? 2
                                   : launch && (launch->flags & DSG_LAUNCH_ID_BUCKETS) ? 1
                                                                                      : 0,
                                   core_mode);

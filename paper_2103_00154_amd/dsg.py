@@ -56,6 +56,8 @@ LAUNCH_BIN_REGIONS = 1
 LAUNCH_NO_PROGRESS = 2
 #: dsg_launch.flags bits: degree-update records keyed by neighbour id in
 #: every pass that leaves survivors (graphs of at most 2^25 vertices), or never
+#: (by default: passes that leave more than 65536 survivors and walk at least
+#: 2^25 adjacency entries)
 LAUNCH_ID_BUCKETS = 4
 LAUNCH_NO_ID_BUCKETS = 8
 

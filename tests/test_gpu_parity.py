@@ -135,8 +135,10 @@ def test_config_rmat20(dsg, eps):
     g = _rmat20()
     check(g, eps)
     check(g, eps, launch={"bin_regions": True})
-    # the first passes leave more survivors than the walk's filter holds, so
-    # by default they key their records by neighbour id; here they do not
+    # the first passes leave more survivors than the walk's filter holds;
+    # they walk too few entries to key their records by neighbour id by
+    # default, so both ways are forced here
+    check(g, eps, launch={"id_buckets": True})
     check(g, eps, launch={"id_buckets": False})
 
 
