@@ -217,12 +217,14 @@ def test_contract_violations_reach_the_result():
 def test_one_sided_rows_with_bin_regions_are_an_internal_error():
     # more decrement records for vertex 0 than its degree: with bin regions
     # forced they overrun its region, are dropped, and the peel reports
-    # DSG_EINTERNAL (the kernels end normally); the per-tile layout reports
-    # the same through the edge count
+    # DSG_EINTERNAL (the kernels end normally); the per-tile layout and the
+    # records keyed by neighbour id (which count all 10 and have no region to
+    # overrun) report the same through the edge count
     import torch
     from paper_2103_00154_amd import dsg
     rp, ci = (torch.from_numpy(a).cuda() for a in _one_sided())
-    for launch in ({"bin_regions": True}, {"bin_regions": True, "pass_batch": 1}, None):
+    for launch in ({"bin_regions": True}, {"bin_regions": True, "pass_batch": 1}, None,
+                   {"id_buckets": True}, {"id_buckets": True, "pass_batch": 1}):
         with pytest.raises(dsg.DsgError) as exc:
             dsg.peel(rp, ci, (1, 10), m=6, launch=launch)
         assert exc.value.status == dsg.DSG_EINTERNAL
