@@ -43,7 +43,6 @@ constexpr int64_t kDirectRecords = 65536;        // at most this many records: c
 // group of kIdGroupTiles walk tiles; the apply step counts the positions of
 // one bucket in LDS and resolves liveness and rank from the bucket's
 // directory words, staged once per work item.
-constexpr int kXcds = 8;                         // accelerator dies of an MI355X (one L2 each)
 constexpr int kIdShift = 15;
 constexpr int kIdWidth = 1 << kIdShift;          // ids per bucket: the k_apply counters
 constexpr int kIdWords = kIdWidth / 32;          // rank-directory words per bucket
@@ -122,6 +121,7 @@ struct alignas(256) DevState {
     int32_t id_nb;        // walk mode 2: buckets (ceil(n / kIdWidth))
     int32_t id_groups;    //   record groups of the current pass
     int32_t id_words;     //   rank-directory words (ceil(n / 32))
+    uint32_t apply_next;  //   apply items taken after each workgroup's first
     // k-core levels (CBDS-P phase 1): the threshold is the level k and stays
     // there while passes remove vertices; a pass that removes none ends the
     // level, and the next level is the least degree left

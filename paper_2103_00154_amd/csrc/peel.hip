@@ -46,9 +46,10 @@
 //                   bucket, each over a range of record groups;
 //   k_apply         counts a bucket's positions in LDS, finds the survivors
 //                   among them from the bucket's rank-directory words and
-//                   subtracts their counts (or writes them as partial rows,
-//                   indexed by position, when a bucket has several items);
-//   k_reduce        sums those partial rows into the survivors' degrees;
+//                   writes their counts as the item's partial row, indexed
+//                   by position (workgroups take items from a counter);
+//   k_reduce        sums each bucket's partial rows into its survivors'
+//                   degrees;
 //   k_walk_finish   (phase 1) completes the pass (|V|, |E|, best, threshold)
 //                   from the counts that reached a survivor.
 //
@@ -214,6 +215,7 @@ __global__ void k_init_state(Work w, const int32_t* __restrict__ rp, int64_t n, 
     st->id_nb = 0;
     st->id_groups = 0;
     st->id_words = 0;
+    st->apply_next = 0;
     if (rp[0] != 0 || (int64_t)rp[n] != 2 * m) {
         st->status = kStBadRowPtr;
         st->done = 1;
@@ -1306,8 +1308,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_ids(Work w, const int32_t* __re
 // Walk mode 2: the apply work items, planned after the walk.  Bucket b gets
 // one item and its share of up to kTargetItems more, in proportion to the
 // adjacency entries of its ids (which bound its records and track them);
-// each item covers a contiguous range of the pass's record groups.  A bucket
-// with one item lets it update the degrees itself.
+// each item covers a contiguous range of the pass's record groups.
 __device__ void plan_id_items(const Work& w, const int32_t* __restrict__ rp, int64_t n,
                               int32_t* red) {
     DevState* st = w.st;
@@ -1347,6 +1348,7 @@ __device__ void plan_id_items(const Work& w, const int32_t* __restrict__ rp, int
     if (threadIdx.x == 0) {
         st->n_items = total;
         st->apply_direct = 0;
+        st->apply_next = 0;
     }
 }
 
@@ -1384,10 +1386,10 @@ __global__ __launch_bounds__(kBlock) void k_walk_finish(Work w, const int32_t* _
 // Walk mode 2: an item counts its bucket's records over its range of record
 // groups, then resolves every position from the bucket's rank-directory
 // words (staged once): a position whose live bit is set is a survivor, and
-// its count goes to that survivor's degree when the item is its bucket's
-// only one, else to the item's partial row at the position (k_reduce sums
-// the rows).  Counts that reach a survivor are this workgroup's part of the
-// pass's decrements.
+// its count goes to the item's partial row at the position (k_reduce sums a
+// bucket's rows into its survivors' degrees).  Counts that reach a survivor
+// are this workgroup's part of the pass's decrements.
+//
 // The eight records of chunk k (records 8k .. 8k + 7 of the group) that lie
 // in the run [s, e) are counted; the others go to this lane's spare counter
 // past the bucket's (no branch, and no two lanes share a spare).
@@ -1411,23 +1413,19 @@ __device__ void apply_ids(const Work& w, int32_t* cnt, uint32_t* se, uint2* sdir
     const int64_t G = st->id_groups;
     const uint32_t* __restrict__ toff2 = reinterpret_cast<const uint32_t*>(w.toff);
     const int64_t nwords = st->id_words;
-    int32_t* __restrict__ deg = deg_out(w, st->pass);  // the pass completes after this update
     const uint16_t* __restrict__ recs = w.recs;
     const int tid = threadIdx.x;
     unsigned long long cross = 0;
-    // Items are numbered by bucket, and one group region holds the runs of
-    // every bucket side by side, so items of neighbouring buckets read the
-    // same lines.  Workgroups are dispatched to the XCDs in turn (blockIdx.x
-    // modulo kXcds), each with its own L2: every XCD takes one contiguous
-    // eighth of the items.
-    const int xcds = gridDim.x % kXcds == 0 ? kXcds : 1;
-    const int32_t x = (int32_t)(blockIdx.x % xcds), per = (int32_t)(gridDim.x / xcds);
-    const int32_t it0 = (int32_t)((int64_t)n_items * x / xcds);
-    const int32_t it1 = (int32_t)((int64_t)n_items * (x + 1) / xcds);
-    for (int32_t it = it0 + (int32_t)(blockIdx.x / xcds); it < it1; it += per) {
+    // Items differ in size (R-MAT's hub buckets are heavy), so after its
+    // first item a workgroup takes the next free one from a device counter;
+    // the take is issued when an item starts and read when it ends.
+    __shared__ int32_t s_next;
+    for (int32_t it = blockIdx.x; it < n_items;) {
+        int32_t next = 0;
+        if (tid == 0)
+            next = (int32_t)gridDim.x + (int32_t)atomicAdd(&w.st->apply_next, 1u);
         const int4 item = w.items[it];
         const int32_t b = item.x, npos = item.w;
-        const bool alone = w.bin_items[b].y == 1;
         const int64_t w0 = (int64_t)b * kIdWords;
         const int32_t nw = (int32_t)std::min<int64_t>(kIdWords, nwords - w0);
         for (int i = tid; i < npos; i += kApplyBlock) cnt[i] = 0;
@@ -1495,36 +1493,19 @@ __device__ void apply_ids(const Work& w, int32_t* cnt, uint32_t* se, uint2* sdir
             }
             __syncthreads();  // se is reloaded for the next groups; counts are done
         }
-        // positions tid + k * kApplyBlock, eight at a time: the survivors'
-        // degrees are all loaded (unconditionally, rank 0 standing in for
-        // the other positions) before any is stored
-        static_assert(kIdWidth % (8 * kApplyBlock) == 0, "whole rounds of eight positions");
-        for (int p0 = tid; p0 < npos; p0 += 8 * kApplyBlock) {
-            int32_t c[8], r[8], dv[8];
-            bool live[8];
-#pragma unroll
-            for (int h = 0; h < 8; ++h) {
-                const int p = p0 + h * kApplyBlock;
-                const uint2 d = sdir[std::min(p, npos - 1) >> 5];
-                const uint32_t bit = 1u << (p & 31);
-                live[h] = p < npos && (d.x & bit);
-                c[h] = live[h] ? cnt[p] : 0;
-                r[h] = live[h] ? (int32_t)(d.y + __popc(d.x & (bit - 1u))) : 0;
-                cross += (uint32_t)c[h];
-            }
-            if (alone) {
-#pragma unroll
-                for (int h = 0; h < 8; ++h) dv[h] = deg[r[h]];
-#pragma unroll
-                for (int h = 0; h < 8; ++h)
-                    if (c[h]) deg[r[h]] = dv[h] - c[h];
-            } else {
-#pragma unroll
-                for (int h = 0; h < 8; ++h)
-                    if (live[h]) w.partial[(int64_t)it * stride + p0 + h * kApplyBlock] = c[h];
+        // every live position's count goes to the item's partial row (stores
+        // only: no round trip holds up the item); k_reduce applies the rows
+        for (int p = tid; p < npos; p += kApplyBlock) {
+            const uint2 d = sdir[p >> 5];
+            if (d.x & (1u << (p & 31))) {
+                const int32_t c = cnt[p];
+                cross += (uint32_t)c;
+                w.partial[(int64_t)it * stride + p] = c;
             }
         }
-        __syncthreads();  // cnt and sdir are reused by the next item
+        if (tid == 0) s_next = next;
+        __syncthreads();  // cnt and sdir are reused by the next item; s_next is set
+        it = s_next;
     }
     const unsigned long long all = block_sum<unsigned long long, kNW>(cross, redc);
     if (tid == 0) w.wpart[blockIdx.x] = all;
@@ -1631,16 +1612,14 @@ __global__ __launch_bounds__(kBlock) void k_reduce(Work w) {
     const int64_t nL = st->nL;
     const int32_t stride = st->part_stride;
     if (st->walk_mode == 2) {
-        // walk mode 2: a survivor whose bucket has several items gets the
-        // sum of their partial rows at its position; the pass has not
-        // advanced yet
+        // walk mode 2: every survivor gets the sum of its bucket's items'
+        // partial rows at its position; the pass has not advanced yet
         int32_t* __restrict__ deg = deg_out(w, st->pass);
         const int32_t* __restrict__ lst = live_out(w, st->pass);
         for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < nL;
              r += (int64_t)gridDim.x * kBlock) {
             const int32_t v = lst[r];
             const int2 bi = w.bin_items[v >> kIdShift];
-            if (bi.y < 2) continue;
             const int32_t* __restrict__ p =
                 w.partial + (int64_t)bi.x * stride + (v & (kIdWidth - 1));
             int32_t sum = 0;
