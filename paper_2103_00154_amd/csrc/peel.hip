@@ -1268,8 +1268,8 @@ __global__ __launch_bounds__(kBlock) void k_walk_ids(Work w, const int32_t* __re
             }
             __syncthreads();  // own[] and bas[] are rebuilt for the next tile
         }
-        // bucket offsets: exclusive prefix of the counts, the group's row of
-        // the offset table, and the start of every bucket's cursor
+        // bucket offsets: exclusive prefix of the counts, the group's column
+        // of the offset table, and the start of every bucket's cursor
         int32_t all;
         {
             const int q = (nb + kBlock - 1) / kBlock;
