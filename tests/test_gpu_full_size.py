@@ -41,3 +41,19 @@ def test_rmat24_planted_full_parity():
     assert 2 * 11 * r.num * len(ids) >= 10 * e_p * r.den
     overlap = int(np.count_nonzero(mask[r.best.cpu().numpy()]))
     say(f"planted density {e_p}/{len(ids)}; S~ {r.num}/{r.den}; |S~ & P| = {overlap}")
+
+
+@pytest.mark.parametrize("eps", [(1, 10), (0, 1)])
+def test_power_law_graph_with_id_keyed_passes_by_default(eps):
+    # a Chung-Lu graph of 5 M vertices: its first pass leaves more than
+    # 65,536 survivors and walks more than 2^25 entries, so by default it
+    # keys its degree records by neighbour id, and later passes gather
+    # survivor ranks; every output is compared with the oracle
+    from paper_2103_00154_amd import dsg
+    g = inputs.chung_lu(5_000_000, 24, 2.3, 5)
+    say(f"case chung_lu n={g.n} m={g.m} eps={eps[0]}/{eps[1]}: oracle")
+    o = oracle.peel_graph(g, *eps)
+    rp, ci = to_device(g)
+    r = dsg.peel(rp, ci, eps, removed_at=True, trace=True)
+    assert any(t["s_out"] > 65536 and t["walked"] >= 1 << 25 for t in r.trace), r.trace[:2]
+    assert_same(r, o, g.n)
