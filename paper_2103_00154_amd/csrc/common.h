@@ -36,7 +36,8 @@ constexpr int64_t kTargetItems = 512;            // apply work items aimed for p
 constexpr int64_t kDirectRecords = 65536;        // at most this many records: counts applied by atomics
 
 // Neighbour-id buckets of the degree update (walk mode 2, passes that leave
-// more than kFiltBits survivors).  Bucket b holds the ids
+// more than kFiltBits survivors and walk at least kIdMinEntries entries).
+// Bucket b holds the ids
 // [b * kIdWidth, (b + 1) * kIdWidth), i.e. kIdWords consecutive rank-directory
 // words.  The walk writes no survivor rank: every walked entry becomes a
 // 16-bit position inside its neighbour's bucket, sorted by bucket in LDS per

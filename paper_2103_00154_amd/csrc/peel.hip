@@ -34,9 +34,10 @@
 //   k_reduce        subtracts every bin's partial rows from the survivors'
 //                   degrees (1 to 16 lanes per rank, by the rows per bin).
 //
-// A pass that leaves more survivors than the walk's survivor filter holds
-// keys its records by neighbour id instead (walk mode 2), so that no walked
-// entry gathers from the rank directory:
+// A pass that leaves more survivors than the walk's survivor filter holds,
+// and walks at least kIdMinEntries entries, keys its records by neighbour id
+// instead (walk mode 2), so that no walked entry gathers from the rank
+// directory:
 //
 //   k_walk_ids      takes the walk list in groups of kIdGroupTiles tiles and
 //                   writes every walked entry as its neighbour's 16-bit
