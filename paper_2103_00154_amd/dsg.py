@@ -225,6 +225,10 @@ def peel(row_ptr, col_idx, eps=(1, 10), *, m: int | None = None, extract: bool =
     which each vertex failed (or pass a preallocated int32[n] tensor).
     ``workspace`` is an optional uint8 device tensor of at least
     :func:`workspace_bytes` bytes; without it the library allocates one.
+    ``launch`` overrides the launch shape (``mark_grid``, ``walk_grid``,
+    ``pass_batch``) and sets flags: ``bin_regions``, ``no_progress``, and
+    ``id_buckets`` (True: key the degree records of every pass by neighbour
+    id; False: never); results never depend on it.
     """
     import torch
     _check_int32_cuda("row_ptr", row_ptr)
