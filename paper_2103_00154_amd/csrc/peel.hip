@@ -1048,11 +1048,22 @@ __global__ __launch_bounds__(kBlock) void k_walk(Work w, const int32_t* __restri
     }
 
     uint32_t cross = 0;
+    // the walk-list rows that own a tile's first entry and the next tile's
+    // (nA - 1 past the last tile), loaded one tile ahead
+    auto row_of = [&](int32_t t) { return t < ntiles ? w.tile_first[t] : nA - 1; };
+    int32_t i0_next = 0, ihi_next = 0;
+    if ((int32_t)blockIdx.x < ntiles) {
+        i0_next = row_of(blockIdx.x);
+        ihi_next = row_of(blockIdx.x + 1);
+    }
     for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const uint32_t e0 = (uint32_t)t * kWalkTile;
         const int32_t len = (int32_t)min((uint32_t)kWalkTile, total - e0);
-        const int32_t i0 = w.tile_first[t];
-        const int32_t ihi = (t + 1 < ntiles) ? w.tile_first[t + 1] : nA - 1;
+        const int32_t i0 = i0_next, ihi = ihi_next;
+        if (t + (int32_t)gridDim.x < ntiles) {
+            i0_next = row_of(t + gridDim.x);
+            ihi_next = row_of(t + gridDim.x + 1);
+        }
         if (i0 < 0 || ihi >= nA || ihi < i0 || ihi - i0 + 1 > kWalkTile + 1) {
             // cannot happen for a consistent walk list; never index with it
             if (tid == 0) st->status = kStInvariant;
@@ -1228,9 +1239,16 @@ __global__ __launch_bounds__(kBlock) void k_walk_ids(Work w, const int32_t* __re
     uint16_t* stage = reinterpret_cast<uint16_t*>(pool);
     __shared__ int32_t hist[kIdMaxBuckets];  // bucket counts, then cursors
     __shared__ int32_t red[kWaves];
+    __shared__ int32_t s_row[kIdGroupTiles + 1];  // row owning each tile's first entry
 
     for (int32_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
         for (int b = tid; b < nb; b += kBlock) hist[b] = 0;
+        // the rows of the group's tiles, all loaded at once (nA - 1 past the
+        // last tile of the pass)
+        if (tid <= kIdGroupTiles) {
+            const int32_t t = g * kIdGroupTiles + tid;
+            s_row[tid] = t < ntiles ? w.tile_first[t] : nA - 1;
+        }
         __syncthreads();
         uint32_t key[kIdGroupTiles][kWalkItems];  // neighbour id, or kNone
 #pragma unroll
@@ -1242,8 +1260,8 @@ __global__ __launch_bounds__(kBlock) void k_walk_ids(Work w, const int32_t* __re
             if (t >= ntiles) continue;
             const uint32_t e0 = (uint32_t)t * kWalkTile;
             const int32_t len = (int32_t)min((uint32_t)kWalkTile, total - e0);
-            const int32_t i0 = w.tile_first[t];
-            const int32_t ihi = (t + 1 < ntiles) ? w.tile_first[t + 1] : nA - 1;
+            const int32_t i0 = s_row[s];
+            const int32_t ihi = s_row[s + 1];
             if (i0 < 0 || ihi >= nA || ihi < i0 || ihi - i0 + 1 > kWalkTile + 1) {
                 // cannot happen for a consistent walk list; never index with it
                 if (tid == 0) st->status = kStInvariant;
