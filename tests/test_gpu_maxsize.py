@@ -112,6 +112,29 @@ def test_adjacency_entries_just_below_int32_limit():
     torch.cuda.empty_cache()
 
 
+def test_id_keyed_pass_with_the_most_buckets():
+    # n = 2^25, the most vertices whose passes may key their degree records
+    # by neighbour id (1024 buckets of 32768 ids), and 2m = 1.61 G: pass 1
+    # walks 537 M entries and leaves 16.8 M survivors, so by default it takes
+    # the id-keyed walk with about 32,800 record groups
+    import torch
+    from paper_2103_00154_amd import dsg
+    n_side = 1 << 24
+    say(f"building bridged cliques on the GPU: n = {2 * n_side}, 2m = {96 * n_side}")
+    rp, ci = bridged_cliques(n_side, "cuda")
+    ws = dsg.alloc_workspace(2 * n_side, ci.numel() // 2)
+    for eps in ((1, 10), (0, 1), (1, 1)):
+        say(f"peel eps = {eps[0]}/{eps[1]}")
+        r = dsg.peel(rp, ci, eps, removed_at=True, trace=True, workspace=ws)
+        check_closed_form(r, n_side, eps)
+        if tuple(eps) != (1, 1):
+            t = r.trace[0]
+            assert t["s_out"] > 65536 and t["walked"] >= 1 << 25, t
+        del r
+    del rp, ci, ws
+    torch.cuda.empty_cache()
+
+
 def test_batch_with_col_idx_offsets_beyond_int32():
     # three bridged-clique graphs of 768 M adjacency entries each, back to
     # back: the third one starts past entry 2^31 of the concatenated arrays,
